@@ -1,0 +1,227 @@
+"""Closed-form Stokes-flow solution of the paper (Sec. 2, App. A, App. C) in
+float64 -- TEST INFRASTRUCTURE ONLY (tests, smoke check and benchmark
+baseline may import it; the product path never does).
+
+Coordinates are the paper's: origin on the interface, fluid a on top
+(0 <= y <= a), fluid b below (-b <= y <= 0), heating wavelength l,
+omega = 2 pi / l, hot spot at x = 0.
+
+Velocity convention: the paper's stream-function definition (Sec. 2) is
+garbled; the printed velocity components u^gamma, v^gamma are used as they
+stand.  They equal u = d psi / dy, v = -d psi / dx of
+psi = U_t [C2 y cosh wy + (C3 + C4 y) sinh wy] sin wx
+    + U_tt/2 [D2 y cosh 2wy + (D3 + D4 y) sinh 2wy] sin 2wx,
+which is divergence-free; the tests check that and the boundary conditions.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Channel:
+    """Geometry, properties and surface-tension law of the two-layer channel."""
+    a: float                 # top (fluid a) thickness
+    b: float                 # bottom (fluid b) thickness
+    l: float                 # heating wavelength
+    mu_b: float              # dynamic viscosity of the bottom fluid
+    mu_ratio: float = 1.0    # mu_a / mu_b  (Eq. three)
+    k_ratio: float = 1.0     # k_a / k_b
+    sigma_T: float = 0.0     # Eq. (ST_SRF) linear coefficient
+    sigma_TT: float = 0.0    # Eq. (ST_SRF) quadratic coefficient
+    T_ref: float = 1.0
+    T_h: float = 1.0
+    T_c: float = 1.0
+    dT: float = 1.0
+
+    @property
+    def omega(self) -> float:
+        return 2.0 * np.pi / self.l
+
+    @property
+    def at(self) -> float:   # a tilde
+        return self.a * self.omega
+
+    @property
+    def bt(self) -> float:   # b tilde
+        return self.b * self.omega
+
+
+def f_fun(at, bt, kt):
+    """App. A, Eq. (f)."""
+    return 1.0 / (kt * np.sinh(bt) * np.cosh(at) + np.sinh(at) * np.cosh(bt))
+
+
+def g_fun(at, bt, kt):
+    """Sec. 2: g = sinh(a~) f(a~, b~, k~)."""
+    return np.sinh(at) * f_fun(at, bt, kt)
+
+
+def h_fun(at, bt, mt):
+    """Sec. 2: h(a~, b~, mu~) in the expression for U_t."""
+    Da = np.sinh(at) ** 2 - at ** 2
+    Db = np.sinh(bt) ** 2 - bt ** 2
+    return Da * Db / (mt * Db * (np.sinh(2 * at) - 2 * at) + Da * (np.sinh(2 * bt) - 2 * bt))
+
+
+def h1_fun(at, bt, mt):
+    """Sec. 2: h~_1(a~, b~, mu~) = h(2a~, 2b~, mu~), written out as printed."""
+    Da = np.sinh(2 * at) ** 2 - 4 * at ** 2
+    Db = np.sinh(2 * bt) ** 2 - 4 * bt ** 2
+    return Da * Db / (mt * Db * (np.sinh(4 * at) - 4 * at) + Da * (np.sinh(4 * bt) - 4 * bt))
+
+
+def interface_mean_T(c: Channel) -> float:
+    """Linear part of the temperature on the interface (Eq. Ta at y = 0)."""
+    return (c.T_c * c.k_ratio * c.b + c.T_h * c.a) / (c.a + c.b * c.k_ratio)
+
+
+def U_t(c: Channel) -> float:
+    """Sec. 2, Eq. (Umaxexpression)."""
+    g = g_fun(c.at, c.bt, c.k_ratio)
+    h = h_fun(c.at, c.bt, c.mu_ratio)
+    return -(c.dT / c.mu_b) * g * h * (c.sigma_T + 2 * c.sigma_TT * (interface_mean_T(c) - c.T_ref))
+
+
+def U_tt(c: Channel) -> float:
+    """Sec. 2: U_tt = -(sigma_TT dT^2 / mu_b) g^2 h~_1."""
+    g = g_fun(c.at, c.bt, c.k_ratio)
+    return -(c.sigma_TT * c.dT ** 2 / c.mu_b) * g ** 2 * h1_fun(c.at, c.bt, c.mu_ratio)
+
+
+def constants(c: Channel):
+    """Sec. 2: C_j^gamma and D_j^gamma (j = 1..4) as printed."""
+    a, b, at, bt = c.a, c.b, c.at, c.bt
+    Db1 = np.sinh(bt) ** 2 - bt ** 2
+    Da1 = np.sinh(at) ** 2 - at ** 2
+    Db2 = np.sinh(2 * bt) ** 2 - 4 * bt ** 2
+    Da2 = np.sinh(2 * at) ** 2 - 4 * at ** 2
+    C = {
+        "b": (0.0, np.sinh(bt) ** 2 / Db1, -b * bt / Db1, (np.sinh(2 * bt) - 2 * bt) / (2 * Db1)),
+        "a": (0.0, np.sinh(at) ** 2 / Da1, -a * at / Da1, -(np.sinh(2 * at) - 2 * at) / (2 * Da1)),
+    }
+    D = {
+        "b": (0.0, np.sinh(2 * bt) ** 2 / Db2, -2 * b * bt / Db2, (np.sinh(4 * bt) - 4 * bt) / (2 * Db2)),
+        "a": (0.0, np.sinh(2 * at) ** 2 / Da2, -2 * a * at / Da2, -(np.sinh(4 * at) - 4 * at) / (2 * Da2)),
+    }
+    return C, D
+
+
+def temperature(c: Channel, x, y):
+    """Eqs. (Ta), (Tb): two-layer conduction field (k jump at y = 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    w, kt, f = c.omega, c.k_ratio, f_fun(c.at, c.bt, c.k_ratio)
+    den = c.a + c.b * kt
+    Ta = ((c.T_c - c.T_h) * y + c.T_c * kt * c.b + c.T_h * c.a) / den \
+        + c.dT * f * np.sinh(c.at - w * y) * np.cos(w * x)
+    Tb = (kt * (c.T_c - c.T_h) * y + c.T_c * kt * c.b + c.T_h * c.a) / den \
+        + c.dT * f * (np.sinh(c.at) * np.cosh(w * y) - kt * np.sinh(w * y) * np.cosh(c.at)) * np.cos(w * x)
+    return np.where(y >= 0, Ta, Tb)
+
+
+def velocity(c: Channel, x, y):
+    """Sec. 2: u^gamma(x, y), v^gamma(x, y) for gamma = a (y >= 0), b (y < 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    w = c.omega
+    Ut, Utt = U_t(c), U_tt(c)
+    C, D = constants(c)
+    out_u, out_v = [], []
+    for key in ("a", "b"):
+        _, C2, C3, C4 = C[key]
+        _, D2, D3, D4 = D[key]
+        u = Ut * ((C2 + w * (C3 + C4 * y)) * np.cosh(w * y) + (C4 + w * C2 * y) * np.sinh(w * y)) * np.sin(w * x) \
+            + 0.5 * Utt * ((D2 + 2 * w * (D3 + D4 * y)) * np.cosh(2 * w * y)
+                           + (D4 + 2 * w * D2 * y) * np.sinh(2 * w * y)) * np.sin(2 * w * x)
+        v = -w * Ut * (C2 * y * np.cosh(w * y) + (C3 + C4 * y) * np.sinh(w * y)) * np.cos(w * x) \
+            - w * Utt * (D2 * y * np.cosh(2 * w * y) + (D3 + D4 * y) * np.sinh(2 * w * y)) * np.cos(2 * w * x)
+        out_u.append(u)
+        out_v.append(v)
+    upper = y >= 0
+    return np.where(upper, out_u[0], out_u[1]), np.where(upper, out_v[0], out_v[1])
+
+
+def interface_velocity(c: Channel, x):
+    """Sec. 2 boundary condition iii: u(x, 0) = U_t sin wx + U_tt/2 sin 2wx."""
+    x = np.asarray(x, dtype=np.float64)
+    return U_t(c) * np.sin(c.omega * x) + 0.5 * U_tt(c) * np.sin(2 * c.omega * x)
+
+
+def U_s(c: Channel) -> float:
+    """App. C, Eq. (U_s): characteristic thermocapillary velocity."""
+    C1 = (c.T_h * (c.a / c.b) + c.T_c * c.k_ratio) / ((c.a / c.b) + c.k_ratio)
+    C2 = c.dT * np.sinh(c.at) / (c.k_ratio * np.cosh(c.at) * np.sinh(c.bt) + np.cosh(c.bt) * np.sinh(c.at))
+    return (c.dT / c.mu_b) * (c.b / c.l) * (c.sigma_T + 2 * c.sigma_TT * (C1 + C2 - c.T_ref))
+
+
+def capillary_number(c: Channel, sigma0: float) -> float:
+    """Eq. (ReMaCa): Ca = U mu_b / sigma_0 with U = |U_s|."""
+    return abs(U_s(c)) * c.mu_b / sigma0
+
+
+def ygb_velocity(sigma_T: float, gradT: float, R: float, mu_b: float,
+                 k_ratio: float, mu_ratio: float) -> float:
+    """Sec. 5.1: U* = -sigma_T |grad T| R / mu_b, U_YGB = 2 U* / ((2 + k~)(2 + 3 mu~))."""
+    Ustar = -sigma_T * abs(gradT) * R / mu_b
+    return 2 * Ustar / ((2 + k_ratio) * (2 + 3 * mu_ratio))
+
+
+def channel_from_config(cfg: dict) -> Channel:
+    """Map a lattice configuration (walls half-way outside rows 0 and ny-1,
+    interface plane at y = b - 1/2) to the analytic channel."""
+    nx, ny, b = int(cfg["nx"]), int(cfg["ny"]), float(cfg["b"])
+    rho_b = float(cfg.get("rho_b", 1.0))
+    return Channel(a=ny - b, b=b, l=nx / int(cfg["n_waves"]), mu_b=float(cfg["mu_b"]),
+                   mu_ratio=float(cfg["mu_a"]) / float(cfg["mu_b"]),
+                   k_ratio=float(cfg["k_a"]) / float(cfg["k_b"]),
+                   sigma_T=float(cfg["sigma_T"]), sigma_TT=float(cfg["sigma_TT"]),
+                   T_ref=float(cfg["T_ref"]), T_h=float(cfg["T_h"]), T_c=float(cfg["T_c"]),
+                   dT=float(cfg["dT"]))
+
+
+def lattice_coords(cfg: dict):
+    """Paper coordinates (x, y) of lattice node centres, arrays [ny][nx]."""
+    nx, ny, b = int(cfg["nx"]), int(cfg["ny"]), float(cfg["b"])
+    i = np.arange(nx, dtype=np.float64)
+    j = np.arange(ny, dtype=np.float64)
+    X, Y = np.meshgrid(i, j - (b - 0.5))
+    return X, Y
+
+
+def count_rolls(uy: np.ndarray, cfg: dict) -> int:
+    """Number of convection rolls: sign changes (periodic in x) of the
+    vertical velocity along the mid-line of each layer, summed over the two
+    layers.  Values below 1e-3 of the row's peak are ignored."""
+    ny = uy.shape[0]
+    b = float(cfg["b"])
+    rows = [int(round(b / 2.0 - 0.5)), int(round(b + (ny - b) / 2.0 - 0.5))]
+    total = 0
+    for r in rows:
+        v = uy[r]
+        thr = 1e-3 * np.max(np.abs(v))
+        s = np.sign(np.where(np.abs(v) > thr, v, 0.0))
+        s = s[s != 0]
+        if s.size == 0:
+            continue
+        total += int(np.sum(s != np.roll(s, 1)))
+    return total
+
+
+def interface_profile(ux: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """u_x(x) on the phi = 1/2 level, linearly interpolated between the two
+    rows whose phi brackets 1/2 (one crossing per column is assumed)."""
+    ny, nx = phi.shape
+    out = np.zeros(nx)
+    for i in range(nx):
+        col = phi[:, i] - 0.5
+        k = np.nonzero((col[:-1] >= 0) & (col[1:] < 0))[0]
+        if k.size == 0:
+            out[i] = np.nan
+            continue
+        j = int(k[0])
+        t = col[j] / (col[j] - col[j + 1])
+        out[i] = (1 - t) * ux[j, i] + t * ux[j + 1, i]
+    return out

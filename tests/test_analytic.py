@@ -1,0 +1,195 @@
+"""Pins of the closed-form solution (Sec. 2, App. A, App. C) against the
+conditions it was derived from and the numbers the paper prints."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import analytic as an
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "printed_numbers.json")))
+
+
+def channels():
+    yield an.Channel(a=128, b=128, l=512, mu_b=0.1, sigma_T=-2e-4, sigma_TT=0.0)
+    yield an.Channel(a=128, b=128, l=512, mu_b=0.1, sigma_T=0.0, sigma_TT=2e-4)
+    yield an.Channel(a=1434, b=614, l=512, mu_b=0.1, mu_ratio=0.5, k_ratio=2.0,
+                     sigma_T=-5e-5, sigma_TT=2e-4)
+    yield an.Channel(a=60, b=20, l=100, mu_b=0.2, mu_ratio=3.0, k_ratio=0.3,
+                     sigma_T=1e-4, sigma_TT=3e-4, T_h=1.5, T_c=0.7, T_ref=1.1, dT=0.4)
+    yield an.Channel(a=20, b=70, l=64, mu_b=0.05, mu_ratio=0.25, k_ratio=4.0,
+                     sigma_T=-1e-4, sigma_TT=1e-4, T_h=2.0, T_c=1.0, T_ref=1.0, dT=0.8)
+
+
+CH = list(channels())
+# channels whose printed hyperbolic form is well conditioned across the whole
+# layer (a~, b~ below ~5); the deep channel is checked at the interface only
+CH_BULK = [c for c in CH if max(c.at, c.bt) < 5.0]
+
+
+def d_dy(fun, x, y, h):
+    return (fun(x, y + h) - fun(x, y - h)) / (2 * h)
+
+
+def d_dx(fun, x, y, h):
+    return (fun(x + h, y) - fun(x - h, y)) / (2 * h)
+
+
+@pytest.mark.parametrize("c", CH)
+def test_temperature_walls_and_interface(c):
+    x = np.linspace(0, c.l, 37)
+    assert np.allclose(an.temperature(c, x, -c.b), c.T_h + c.dT * np.cos(c.omega * x), atol=1e-12)
+    assert np.allclose(an.temperature(c, x, c.a), c.T_c, atol=1e-12)
+    eps = 1e-9
+    Ta = an.temperature(c, x, +eps)
+    Tb = an.temperature(c, x, -eps)
+    assert np.allclose(Ta, Tb, atol=1e-7)
+    # heat-flux continuity k_a dT/dy|0+ = k_b dT/dy|0- (second-order one-sided)
+    h = 1e-4 * min(c.a, c.b)
+    T = lambda Y: an.temperature(c, x, Y)
+    ga = (-3 * T(0.0) + 4 * T(h) - T(2 * h)) / (2 * h)
+    gb = (3 * T(-1e-300) - 4 * T(-h) + T(-2 * h)) / (2 * h)
+    scale = np.max(np.abs(gb)) + 1e-30
+    assert np.max(np.abs(c.k_ratio * ga - gb)) / scale < 1e-6
+
+
+@pytest.mark.parametrize("c", CH_BULK)
+def test_temperature_is_harmonic(c):
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, c.l, 50)
+    for y in (rng.uniform(0.1 * c.a, 0.9 * c.a, 50), -rng.uniform(0.1 * c.b, 0.9 * c.b, 50)):
+        h = 1e-3 * min(c.l, c.a, c.b)
+        T = lambda X, Y: an.temperature(c, X, Y)
+        lap = (T(x + h, y) + T(x - h, y) + T(x, y + h) + T(x, y - h) - 4 * T(x, y)) / h ** 2
+        curv = c.dT * c.omega ** 2
+        assert np.max(np.abs(lap)) < 1e-4 * curv
+
+
+@pytest.mark.parametrize("c", CH_BULK)
+def test_velocity_boundary_conditions(c):
+    x = np.linspace(0, c.l, 41)
+    scale = abs(an.U_t(c)) + abs(an.U_tt(c))
+    for ywall in (-c.b, c.a):
+        u, v = an.velocity(c, x, ywall)
+        assert np.max(np.abs(u)) < 1e-9 * scale
+        assert np.max(np.abs(v)) < 1e-9 * scale
+    for y0 in (0.0, -1e-12):
+        u, v = an.velocity(c, x, y0)
+        assert np.allclose(u, an.interface_velocity(c, x), atol=1e-9 * scale)
+        assert np.max(np.abs(v)) < 1e-9 * scale
+
+
+@pytest.mark.parametrize("c", CH_BULK)
+def test_velocity_is_divergence_free(c):
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0, c.l, 60)
+    h = 1e-4 * min(c.a, c.b)
+    scale = (abs(an.U_t(c)) + abs(an.U_tt(c))) * c.omega
+    U = lambda X, Y: an.velocity(c, X, Y)[0]
+    V = lambda X, Y: an.velocity(c, X, Y)[1]
+    for y in (rng.uniform(0.05 * c.a, 0.95 * c.a, 60), -rng.uniform(0.05 * c.b, 0.95 * c.b, 60)):
+        div = d_dx(U, x, y, h) + d_dy(V, x, y, h)
+        assert np.max(np.abs(div)) < 1e-6 * scale
+
+
+@pytest.mark.parametrize("c", CH_BULK)
+def test_velocity_satisfies_stokes(c):
+    # Sec. 2: the stream function is biharmonic, i.e. the vorticity
+    # w = dv/dx - du/dy is harmonic in each layer.
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, c.l, 40)
+    h = 2e-3 * min(c.a, c.b, c.l)
+    U = lambda X, Y: an.velocity(c, X, Y)[0]
+    V = lambda X, Y: an.velocity(c, X, Y)[1]
+    vort = lambda X, Y: d_dx(V, X, Y, h) - d_dy(U, X, Y, h)
+    scale = (abs(an.U_t(c)) + abs(an.U_tt(c))) * c.omega ** 3
+    for y in (rng.uniform(0.2 * c.a, 0.8 * c.a, 40), -rng.uniform(0.2 * c.b, 0.8 * c.b, 40)):
+        lap = (vort(x + h, y) + vort(x - h, y) + vort(x, y + h) + vort(x, y - h) - 4 * vort(x, y)) / h ** 2
+        assert np.max(np.abs(lap)) < 2e-2 * scale
+
+
+@pytest.mark.parametrize("c", CH)
+def test_marangoni_stress_balance(c):
+    # Sec. 2 condition v: mu_b du^b/dy - mu_a du^a/dy at y = 0 equals
+    # (d sigma / dT) dT/dx on the interface, with T from App. A.  The left
+    # side is differentiated numerically from the velocity field, the right
+    # side from the temperature field, so the check covers U_t, U_tt, f, g,
+    # h, h~_1 and the constants C_j, D_j together.
+    x = np.linspace(0, c.l, 64, endpoint=False)
+    h = 1e-5 * min(c.a, c.b)
+    U = lambda X, Y: an.velocity(c, X, Y)[0]
+    dub0 = (3 * U(x, -1e-300) - 4 * U(x, -h) + U(x, -2 * h)) / (2 * h)
+    dua0 = (-3 * U(x, 0.0) + 4 * U(x, h) - U(x, 2 * h)) / (2 * h)
+    lhs = c.mu_b * dub0 - c.mu_b * c.mu_ratio * dua0
+    T0 = an.temperature(c, x, 0.0)
+    dTdx = (an.temperature(c, x + h, 0.0) - an.temperature(c, x - h, 0.0)) / (2 * h)
+    rhs = (c.sigma_T + 2 * c.sigma_TT * (T0 - c.T_ref)) * dTdx
+    scale = np.max(np.abs(rhs))
+    assert np.max(np.abs(lhs - rhs)) < 1e-4 * scale
+
+
+def test_nf_case_has_no_harmonic_and_srf_case_no_fundamental():
+    nf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=-5e-4, sigma_TT=0.0)
+    assert an.U_tt(nf) == 0.0 and an.U_t(nf) > 0
+    srf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=0.0, sigma_TT=1e-3)
+    assert an.U_t(srf) == 0.0 and an.U_tt(srf) < 0
+
+
+def _lattice_like(c, nx=200, ny=100):
+    # sample the analytic field on a lattice and count rolls like the LBM tests
+    cfg = dict(nx=nx, ny=ny, b=c.b, n_waves=1)
+    X, Y = an.lattice_coords(cfg)
+    _, v = an.velocity(c, X, Y)
+    return an.count_rolls(v, cfg)
+
+
+def test_roll_counts_nf_4_srf_8():
+    # Sec. 6: NF (M2 = 0) shows four rolls, SRF (M1 = 0) shows eight.
+    nf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=-5e-4, sigma_TT=0.0)
+    srf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=0.0, sigma_TT=1e-3)
+    assert _lattice_like(nf) == 4
+    assert _lattice_like(srf) == 8
+
+
+def test_flow_direction_nf_away_srf_toward_hot_spot():
+    # Sec. 6: along the interface the NF moves away from the hot spot at
+    # x = 0, the SRF toward it.
+    nf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=-5e-4, sigma_TT=0.0)
+    srf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=0.0, sigma_TT=1e-3)
+    x = np.array([200 / 8, -200 / 8])
+    unf = an.interface_velocity(nf, x)
+    usrf = an.interface_velocity(srf, x)
+    assert unf[0] > 0 and unf[1] < 0
+    assert usrf[0] < 0 and usrf[1] > 0
+
+
+def _golden_channel(g, M1, M2, mu_b=0.1):
+    sigma0 = g["sigma0"]
+    return an.Channel(a=g["a"], b=g["b"], l=g["l"], mu_b=mu_b, mu_ratio=g["mu_ratio"],
+                      k_ratio=g["k_ratio"], sigma_T=M1 * sigma0, sigma_TT=M2 * sigma0,
+                      T_ref=1.0, T_h=1.0, T_c=1.0, dT=1.0)
+
+
+@pytest.mark.parametrize("key", ["nf_channel_ca", "srf_channel_ca"])
+def test_printed_capillary_numbers_baselines(key):
+    g = GOLD[key]
+    c = _golden_channel(g, g["M1"], g["M2"])
+    # Ca = U_s mu_b / sigma0 does not depend on mu_b; the paper prints 3 digits.
+    assert an.capillary_number(c, g["sigma0"]) == pytest.approx(g["printed_Ca"], rel=0.02)
+
+
+def test_printed_capillary_numbers_deformation():
+    g = GOLD["deformation_ca"]
+    for M2, ca in zip(g["M2"], g["printed_Ca"]):
+        c = _golden_channel(g, g["M1"], M2)
+        assert an.capillary_number(c, g["sigma0"]) == pytest.approx(ca, rel=0.02)
+
+
+def test_printed_ygb_velocity():
+    g = GOLD["ygb_droplet"]
+    U = an.ygb_velocity(g["sigma_T"], g["gradT"], g["R"], g["mu"], 1.0, 1.0)
+    assert U == pytest.approx(g["printed_U_YGB"], rel=1e-3)
+    Ustar = -g["sigma_T"] * g["gradT"] * g["R"] / g["mu"]
+    assert g["rho"] * Ustar * g["R"] / g["mu"] == pytest.approx(g["printed_Re"], rel=1e-9)
+    assert Ustar * g["R"] / g["k"] == pytest.approx(g["printed_Ma"], rel=1e-9)
