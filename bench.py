@@ -1,0 +1,153 @@
+"""Throughput benchmark of the coupled central-moment LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Workload: the throughput channel, 4096 x 2048 nodes, 8 heating wavelengths,
+bottom layer 0.3 of the height, viscosity ratio 0.5, conductivity ratio 2,
+sigma_T = -5e-5, sigma_TT = 2e-4, cold start.  A step is one pass of the
+whole hot path: the fused collide-stream kernel over the lattice, plus (every
+100th step) the float64 residual / conserved-sum reduction and its check
+kernel.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS of the float64 path (value), the float32-deviation
+path alongside, the roofline of the dominant kernel (HBM-bound; algorithmic
+bytes 432 B per node update in float64, 216 B in float32), and the CPU
+oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled-LBM MLUPS & %HBM roofline; time-to-steady warm/batched vs cold FP64"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = {0: 27 * 2 * 8, 1: 27 * 2 * 4}
+# HBM bytes per update measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE of the
+# step kernel, scaled by a plain copy kernel); None until measured for the
+# current kernel.
+MEASURED_TRAFFIC = {0: None, 1: None}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(cfg, prec, steps, warmup, tile):
+    import torch
+
+    from paper_2210_07501_amd import lbm
+
+    ctx = lbm.lbm_create(cfg, precision=prec)
+    if tile:
+        lbm.lbm_set_tile(ctx, *tile)
+    lbm.lbm_init(ctx)
+    nodes, _ = lbm.lbm_info(ctx)
+    lbm.lbm_step(ctx, warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    lbm.lbm_step(ctx, steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    res = lbm.lbm_residual(ctx)
+    # dominant kernel alone: back-to-back step launches timed with HIP events
+    kms = lbm.lbm_profile_steps(ctx, max(20, min(steps, 200)))
+    lbm.lbm_destroy(ctx)
+    return dict(nodes=nodes, ms_total=ms, wall_s=wall, kernel_ms=kms, res=res)
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 oracle, as it stands, on the 256 x 128 sub-run of the same
+    channel geometry (scaled by 1/16), timed on this host's cores."""
+    from oracle import oracle as orc
+    from paper_2210_07501_amd import inputs
+
+    cfg = inputs.throughput_channel(scale=16)
+    o = orc.Oracle(cfg)
+    o.init_cold()
+    t = time.perf_counter()
+    o.step(20)
+    est = (time.perf_counter() - t) / 20
+    n = max(20, int(target_s / max(est, 1e-6)))
+    t = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t
+    nodes = cfg["nx"] * cfg["ny"]
+    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=orc.max_threads(), kind="oracle",
+                sample="256x128 sub-run of the throughput channel (1/16 scale), %d steps from rest, %.1f s" % (n, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=str, default="")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs a single channel (or a batch of channels) "
+              "on one MI355X and has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2210_07501_amd import inputs, lbm
+
+    lbm.load()
+    torch.cuda.set_device(0)
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+    cfg = inputs.throughput_channel()
+    out = {}
+    for prec in (lbm.LBM_FP64, lbm.LBM_FP32_DEV):
+        log("bench: precision %d, %d warmup + %d timed steps on %dx%d" % (prec, args.warmup, args.steps,
+                                                                        cfg["nx"], cfg["ny"]))
+        out[prec] = run_gpu(cfg, prec, args.steps, args.warmup, tile)
+        log("bench: done", out[prec]["ms_total"], "ms")
+
+    def roof(prec):
+        r = out[prec]
+        bpu = BYTES_PER_UPDATE[prec]
+        achieved = bpu * r["nodes"] / (r["kernel_ms"] * 1e-3) / 1e9
+        traffic = MEASURED_TRAFFIC[prec]
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (traffic * r["nodes"]) if traffic else None,
+                "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_update": bpu}
+
+    r64 = out[lbm.LBM_FP64]
+    mlups64 = r64["nodes"] * args.steps / (r64["ms_total"] * 1e-3) / 1e6
+    r32 = out[lbm.LBM_FP32_DEV]
+    mlups32 = r32["nodes"] * args.steps / (r32["ms_total"] * 1e-3) / 1e6
+    line = {
+        "metric": METRIC, "value": round(mlups64, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r64["ms_total"] / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "throughput channel 4096x2048, 8 heating wavelengths, lower layer 0.3, "
+                               "mu ratio 0.5, k ratio 2, sigma_T=-5e-5, sigma_TT=2e-4, cold start",
+                   "nx": cfg["nx"], "ny": cfg["ny"], "precision": "fp64"},
+        "roofline": roof(lbm.LBM_FP64),
+        "fp32_dev": {"value": round(mlups32, 1), "unit": "MLUPS", "dtype": "f32",
+                     "ms_per_step": round(r32["ms_total"] / args.steps, 4), "roofline": roof(lbm.LBM_FP32_DEV)},
+    }
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,689 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// A context holds any number of independent channels.  All of them live in
+// two population buffers (A, B; post-collision values, pull scheme), one
+// node-sized snapshot for the residual, a tile table mapping workgroups to
+// (channel, tile) and one descriptor per channel.  A step is one launch of
+// the fused kernel over every tile of every active channel; every 100th step
+// also takes the float64 residual snapshot and is followed by a per-channel
+// check kernel.  lbm_solve replays a captured HIP graph of 100 steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+    int n_inst = 0;
+    int prec = 0;
+    size_t elem = 8;                   // bytes per stored population
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    lbm_alloc_fn alloc = nullptr;
+    lbm_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    std::vector<lbm_params> params;
+    std::vector<Inst> h_inst;
+    std::vector<int> h_tile_inst;
+    long long total_nodes = 0, total_pop = 0, total_rows = 0;
+    int max_nodes = 0;
+    int n_tiles = 0;
+    int tx = 32, ty = 8;
+    // device memory
+    void* popA = nullptr;
+    void* popB = nullptr;
+    void* phi0 = nullptr;
+    double* snap = nullptr;            // 4 * total_nodes
+    double* partials = nullptr;        // n_tiles * 8 (capacity for the smallest tile)
+    int partial_cap = 0;
+    Inst* d_inst = nullptr;
+    int* d_tile_inst = nullptr;
+    int tile_cap = 0;
+    Result* d_res = nullptr;
+    long long* d_counter = nullptr;
+    double* d_tol = nullptr;
+    int* d_active = nullptr;
+    int* h_active = nullptr;           // pinned
+    std::vector<void*> allocations;
+    size_t device_bytes = 0;
+    // state
+    bool initialised = false;
+    long long steps = 0;               // steps of the channels still active
+    std::vector<char> retired;         // host copy (refreshed by sync points)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_tx = 0, graph_ty = 0, graph_ntiles = -1;
+    std::string last_error;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail_hip(lbm_ctx* c, hipError_t e, const char* what) {
+    std::string s = std::string(what) + ": " + hipGetErrorString(e);
+    if (c) c->last_error = s;
+    g_err = s;
+    (void)hipGetLastError();  // clear the sticky launch error
+    return LBM_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return fail_hip(ctx, e_, #call); \
+    } while (0)
+
+void* dev_alloc(lbm_ctx* c, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (c->alloc) {
+        p = c->alloc(bytes, c->user);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
+    if (p) {
+        c->allocations.push_back(p);
+        c->device_bytes += bytes;
+    }
+    return p;
+}
+
+// Free one temporary allocation made by dev_alloc.
+void dev_release(lbm_ctx* c, void* p) {
+    auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+    if (it == c->allocations.end()) return;
+    c->allocations.erase(it);
+    if (c->free_fn) c->free_fn(p, c->user);
+    else (void)hipFree(p);
+}
+
+void dev_free_all(lbm_ctx* c) {
+    for (void* p : c->allocations) {
+        if (c->free_fn) c->free_fn(p, c->user);
+        else (void)hipFree(p);
+    }
+    c->allocations.clear();
+    c->device_bytes = 0;
+}
+
+int validate(const lbm_params& p) {
+    if (p.nx < 4 || p.ny < 4) return LBM_EINVAL;
+    if (p.n_waves <= 0 || p.nx % p.n_waves != 0) return LBM_EINVAL;
+    if (p.reserved != 0) return LBM_EINVAL;
+    if (!(p.W > 0) || !(p.b > p.W) || !(p.b < p.ny - p.W)) return LBM_EINVAL;
+    if (!(p.M_phi > 0) || !(p.rho_a > 0) || !(p.rho_b > 0)) return LBM_EINVAL;
+    if (!(p.mu_a > 0) || !(p.mu_b > 0) || !(p.k_a > 0) || !(p.k_b > 0)) return LBM_EINVAL;
+    const double vals[] = {p.sigma0, p.sigma_T, p.sigma_TT, p.T_ref, p.T_h, p.dT, p.T_c, p.Fx_ext, p.Fy_ext};
+    for (double v : vals)
+        if (!std::isfinite(v)) return LBM_EINVAL;
+    if ((long long)p.nx * p.ny > (1LL << 31) / 32) return LBM_EINVAL;
+    return LBM_OK;
+}
+
+int tiles_of(const lbm_params& p, int tx, int ty, int* tiles_x) {
+    int txs = (p.nx + tx - 1) / tx, tys = (p.ny + ty - 1) / ty;
+    if (tiles_x) *tiles_x = txs;
+    return txs * tys;
+}
+
+// Build the tile table for the current tile shape over the channels whose
+// host flag says active (all channels when all == true).
+int build_tiles(lbm_ctx* c, bool all) {
+    c->h_tile_inst.clear();
+    for (int k = 0; k < c->n_inst; ++k) {
+        int txs = 0;
+        int nt = tiles_of(c->params[k], c->tx, c->ty, &txs);
+        c->h_inst[k].tiles_x = txs;
+        c->h_inst[k].ntiles = nt;
+        c->h_inst[k].tile0 = (int)c->h_tile_inst.size();
+        if (all || !c->retired[k]) {
+            for (int t = 0; t < nt; ++t) c->h_tile_inst.push_back(k);
+        } else {
+            c->h_inst[k].ntiles = 0;
+        }
+    }
+    c->n_tiles = (int)c->h_tile_inst.size();
+    if (c->n_tiles > c->tile_cap) return LBM_EINVAL;  // capacity sized for the smallest tile at create
+    return LBM_OK;
+}
+
+int upload_tables(lbm_ctx* c) {
+    // descriptors carry an 'active' flag owned by the device; write only the
+    // layout fields, keeping the flag from the device copy
+    std::vector<Inst> cur(c->n_inst);
+    HIPCHK(c, hipMemcpyAsync(cur.data(), c->d_inst, sizeof(Inst) * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n_inst; ++k) c->h_inst[k].active = cur[k].active;
+    HIPCHK(c, hipMemcpyAsync(c->d_inst, c->h_inst.data(), sizeof(Inst) * c->n_inst, hipMemcpyHostToDevice, c->stream));
+    if (c->n_tiles > 0)
+        HIPCHK(c, hipMemcpyAsync(c->d_tile_inst, c->h_tile_inst.data(), sizeof(int) * c->n_tiles,
+                                 hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int grid_of(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
+
+void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
+    a.insts = c->d_inst;
+    a.tile_inst = c->d_tile_inst;
+    a.n_tiles = c->n_tiles;
+    a.src_v = parity ? c->popB : c->popA;
+    a.dst_v = parity ? c->popA : c->popB;
+    a.phi0_v = c->phi0;
+    for (int k = 0; k < 4; ++k) a.snap[k] = c->snap + (size_t)k * c->total_nodes;
+    a.partials = c->partials;
+    for (int k = 0; k < 5; ++k) a.out[k] = nullptr;
+}
+
+void fin_args(lbm_ctx* c, FinArgs& f) {
+    f.insts = c->d_inst;
+    f.results = c->d_res;
+    f.partials = c->partials;
+    for (int k = 0; k < 4; ++k) f.snap[k] = c->snap + (size_t)k * c->total_nodes;
+    f.step_counter = c->d_counter;
+    f.tol = c->d_tol;
+}
+
+// One step starting at global step index `s` (state in buffer s % 2).
+int enqueue_step(lbm_ctx* c, long long s) {
+    StepArgs a;
+    step_args(c, a, (s & 1) != 0);
+    const bool check = (s % CHECK_EVERY) == 0;
+    if (c->n_tiles > 0) {
+        hipError_t e = launch_step(c->prec, a, check ? 1 : 0, grid_of(c->n_tiles), c->tx, c->ty, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "step kernel launch");
+    }
+    if (check) {
+        FinArgs f;
+        fin_args(c, f);
+        hipError_t e = launch_finalize(f, c->n_inst, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "check kernel launch");
+        e = launch_counter(c->d_counter, CHECK_EVERY, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "counter kernel launch");
+    }
+    return LBM_OK;
+}
+
+void drop_graph(lbm_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Capture 100 steps starting at an even global step that is a multiple of
+// the check interval (state in buffer A): check step, check kernel, counter,
+// then 99 plain steps.  The step count is even, so the replay ends in A.
+int build_graph(lbm_ctx* c) {
+    drop_graph(c);
+    hipStream_t cap;
+    HIPCHK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { (void)hipStreamDestroy(cap); return fail_hip(c, e, "hipStreamBeginCapture"); }
+    hipStream_t saved = c->stream;
+    c->stream = cap;
+    int rc = LBM_OK;
+    for (long long s = 0; s < CHECK_EVERY && rc == LBM_OK; ++s) rc = enqueue_step(c, s);
+    c->stream = saved;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (rc != LBM_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail_hip(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { drop_graph(c); return fail_hip(c, e, "hipGraphInstantiate"); }
+    c->graph_tx = c->tx;
+    c->graph_ty = c->ty;
+    c->graph_ntiles = c->n_tiles;
+    return LBM_OK;
+}
+
+int refresh_results(lbm_ctx* c, std::vector<Result>& res) {
+    res.resize(c->n_inst);
+    HIPCHK(c, hipMemcpyAsync(res.data(), c->d_res, sizeof(Result) * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n_inst; ++k) c->retired[k] = res[k].retired_at > 0 ? 1 : 0;
+    return LBM_OK;
+}
+
+long long inst_steps(lbm_ctx* c, const Result& r) { return r.retired_at > 0 ? r.retired_at : c->steps; }
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_strerror(int status) {
+    switch (status) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ENOMEM: return "device allocation failed";
+        case LBM_EDEVICE: return g_err.empty() ? "HIP runtime error" : g_err.c_str();
+        case LBM_EDIVERGED: return "non-finite value in the solution";
+        case LBM_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void* hip_stream,
+               lbm_alloc_fn alloc, lbm_free_fn free_fn, void* user, lbm_ctx** out) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (!params || n_inst <= 0 || (precision != LBM_FP64 && precision != LBM_FP32_DEV)) return LBM_EINVAL;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return LBM_EINVAL;
+    for (int k = 0; k < n_inst; ++k) {
+        int rc = validate(params[k]);
+        if (rc) return rc;
+    }
+    lbm_ctx* c = new lbm_ctx();
+    c->n_inst = n_inst;
+    c->prec = precision;
+    c->elem = precision == LBM_FP64 ? 8 : 4;
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    c->params.assign(params, params + n_inst);
+    c->retired.assign(n_inst, 0);
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail_hip(nullptr, hipErrorUnknown, "hipStreamCreate");
+        }
+        c->own_stream = true;
+    }
+    // layout
+    c->h_inst.resize(n_inst);
+    long long pop = 0, nodes = 0, rows = 0;
+    int min_tile_nodes = 16 * 16;  // smallest compiled tile: capacity for tile tables
+    long long max_tiles = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const lbm_params& p = params[k];
+        Inst& I = c->h_inst[k];
+        std::memset(&I, 0, sizeof(Inst));
+        I.nx = p.nx;
+        I.ny = p.ny;
+        I.active = 1;
+        I.pop_off = pop;
+        I.node_off = nodes;
+        I.row_off = rows;
+        I.W = p.W;
+        I.M_phi = p.M_phi;
+        I.w_phi = 1.0 / (3.0 * p.M_phi + 0.5);
+        I.b = p.b;
+        I.rho_a = p.rho_a; I.rho_b = p.rho_b; I.mu_a = p.mu_a; I.mu_b = p.mu_b;
+        I.k_a = p.k_a; I.k_b = p.k_b;
+        I.s0 = p.sigma0; I.sT = p.sigma_T; I.sTT = p.sigma_TT; I.T_ref = p.T_ref;
+        I.T_h = p.T_h; I.dT = p.dT; I.T_c = p.T_c;
+        I.kx = 2.0 * M_PI / ((double)p.nx / (double)p.n_waves);
+        I.Fx = p.Fx_ext; I.Fy = p.Fy_ext;
+        I.p_r = precision == LBM_FP64 ? 0.0 : 1.0 / 3.0;
+        I.T_r = precision == LBM_FP64 ? 0.0 : p.T_ref;
+        const long long n = (long long)p.nx * p.ny;
+        pop += 27 * n;
+        nodes += n;
+        rows += p.ny + 4;
+        c->max_nodes = std::max<long long>(c->max_nodes, n);
+        // worst case over the compiled tile shapes (16 x 16 and 32 x 8 and 64 x 4 and 64 x 8)
+        long long t = 0;
+        const int shapes[4][2] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}};
+        for (auto& s : shapes) t = std::max<long long>(t, (long long)tiles_of(p, s[0], s[1], nullptr));
+        max_tiles += t;
+    }
+    (void)min_tile_nodes;
+    c->total_pop = pop;
+    c->total_nodes = nodes;
+    c->total_rows = rows;
+    c->tile_cap = (int)max_tiles;
+    c->partial_cap = (int)max_tiles;
+    int rc = LBM_OK;
+    c->popA = dev_alloc(c, (size_t)pop * c->elem);
+    c->popB = dev_alloc(c, (size_t)pop * c->elem);
+    c->phi0 = dev_alloc(c, (size_t)rows * c->elem);
+    c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
+    c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
+    c->d_inst = (Inst*)dev_alloc(c, sizeof(Inst) * n_inst);
+    c->d_tile_inst = (int*)dev_alloc(c, sizeof(int) * max_tiles);
+    c->d_res = (Result*)dev_alloc(c, sizeof(Result) * n_inst);
+    c->d_counter = (long long*)dev_alloc(c, sizeof(long long));
+    c->d_tol = (double*)dev_alloc(c, sizeof(double));
+    c->d_active = (int*)dev_alloc(c, sizeof(int));
+    if (!c->popA || !c->popB || !c->phi0 || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
+        !c->d_res || !c->d_counter || !c->d_tol || !c->d_active) {
+        rc = LBM_ENOMEM;
+    }
+    if (rc == LBM_OK && hipHostMalloc((void**)&c->h_active, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        rc = LBM_ENOMEM;
+    if (rc == LBM_OK) {
+        // reference rows: cold-start tanh phi0(y) for rows -2 .. ny+1 (float32 mode)
+        std::vector<double> rd(rows);
+        for (int k = 0; k < n_inst; ++k) {
+            const lbm_params& p = params[k];
+            for (int j = -2; j <= p.ny + 1; ++j)
+                rd[c->h_inst[k].row_off + j + 2] =
+                    precision == LBM_FP64 ? 0.0 : 0.5 * (1.0 + std::tanh(2.0 * ((p.b - 0.5) - (double)j) / p.W));
+        }
+        if (precision == LBM_FP64) {
+            if (hipMemcpy(c->phi0, rd.data(), rows * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
+        } else {
+            std::vector<float> rf(rd.begin(), rd.end());
+            if (hipMemcpy(c->phi0, rf.data(), rows * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
+        }
+    }
+    if (rc == LBM_OK) rc = build_tiles(c, true);
+    if (rc == LBM_OK) {
+        if (hipMemcpy(c->d_inst, c->h_inst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_tile_inst, c->h_tile_inst.data(), sizeof(int) * c->n_tiles, hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemset(c->d_res, 0, sizeof(Result) * n_inst) != hipSuccess ||
+            hipMemset(c->d_counter, 0, sizeof(long long)) != hipSuccess) {
+            rc = fail_hip(c, hipErrorUnknown, "upload descriptors");
+        }
+        double tol = -1.0;
+        if (rc == LBM_OK && hipMemcpy(c->d_tol, &tol, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail_hip(c, hipErrorUnknown, "upload tolerance");
+    }
+    if (rc != LBM_OK) {
+        lbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    dev_free_all(c);
+    if (c->h_active) (void)hipHostFree(c->h_active);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int lbm_set_tile(lbm_ctx* c, int32_t tx, int32_t ty) {
+    if (!c) return LBM_EINVAL;
+    if (tx == 0 && ty == 0) { tx = 32; ty = 8; }
+    const bool ok = (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 16) || (tx == 64 && ty == 8);
+    if (!ok) return LBM_EINVAL;
+    if (c->initialised && (c->steps % 2) != 0) {
+        // the tile shape may change at any step; buffers are unaffected
+    }
+    c->tx = tx;
+    c->ty = ty;
+    int rc = build_tiles(c, !c->initialised);
+    if (rc) return rc;
+    return upload_tables(c);
+}
+
+int lbm_init(lbm_ctx* c, const double* fields) {
+    if (!c) return LBM_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // reset descriptors (all active), results, counter
+    for (int k = 0; k < c->n_inst; ++k) { c->h_inst[k].active = 1; c->retired[k] = 0; }
+    int rc = build_tiles(c, true);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->d_inst, c->h_inst.data(), sizeof(Inst) * c->n_inst, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_tile_inst, c->h_tile_inst.data(), sizeof(int) * c->n_tiles, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_res, 0, sizeof(Result) * c->n_inst, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_counter, 0, sizeof(long long), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->snap, 0, sizeof(double) * 4 * c->total_nodes, c->stream));
+    InitArgs a;
+    a.insts = c->d_inst;
+    a.dst_v = c->popA;
+    a.phi0_v = c->phi0;
+    a.cold = fields ? 0 : 1;
+    double* dfields = nullptr;
+    if (fields) {
+        for (long long q = 0; q < 4 * c->total_nodes; ++q)
+            if (!std::isfinite(fields[q])) return LBM_EINVAL;
+        dfields = (double*)dev_alloc(c, sizeof(double) * 4 * c->total_nodes);
+        if (!dfields) return LBM_ENOMEM;
+        // host layout: per instance [phi|ux|uy|T]; device: field-major over all nodes
+        for (int k = 0; k < c->n_inst; ++k) {
+            const long long n = (long long)c->params[k].nx * c->params[k].ny;
+            const double* src = fields + 4 * c->h_inst[k].node_off;
+            for (int f = 0; f < 4; ++f)
+                HIPCHK(c, hipMemcpyAsync(dfields + f * c->total_nodes + c->h_inst[k].node_off, src + f * n,
+                                         sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        }
+        for (int f = 0; f < 4; ++f) a.fields[f] = dfields + f * c->total_nodes;
+    } else {
+        for (int f = 0; f < 4; ++f) a.fields[f] = nullptr;
+    }
+    hipError_t e = launch_init(c->prec, a, c->max_nodes, c->n_inst, c->stream);
+    if (e != hipSuccess) return fail_hip(c, e, "init kernel launch");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dfields) dev_release(c, dfields);
+    c->steps = 0;
+    c->initialised = true;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = enqueue_step(c, c->steps);
+        if (rc) return rc;
+        c->steps += 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_solve(lbm_ctx* c, double r_tol, int64_t max_steps, int32_t* n_active) {
+    if (!c || !(r_tol > 0) || max_steps < 0) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    HIPCHK(c, hipMemcpyAsync(c->d_tol, &r_tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int64_t done = 0;
+    int rc = LBM_OK;
+    std::vector<Result> res;
+    // align to the check interval with single steps
+    while (done < max_steps && (c->steps % CHECK_EVERY) != 0) {
+        rc = enqueue_step(c, c->steps);
+        if (rc) break;
+        c->steps += 1;
+        ++done;
+    }
+    int last_active = c->n_inst;
+    while (rc == LBM_OK && done + CHECK_EVERY <= max_steps) {
+        if (!c->graph_exec || c->graph_tx != c->tx || c->graph_ty != c->ty || c->graph_ntiles != c->n_tiles) {
+            rc = build_graph(c);
+            if (rc) break;
+        }
+        hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
+        if (e != hipSuccess) { rc = fail_hip(c, e, "hipGraphLaunch"); break; }
+        c->steps += CHECK_EVERY;
+        done += CHECK_EVERY;
+        e = launch_count_active(c->d_inst, c->n_inst, c->d_active, c->stream);
+        if (e != hipSuccess) { rc = fail_hip(c, e, "count kernel"); break; }
+        e = hipMemcpyAsync(c->h_active, c->d_active, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) { rc = fail_hip(c, e, "hipMemcpyAsync"); break; }
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) { rc = fail_hip(c, e, "hipStreamSynchronize"); break; }
+        const int act = *c->h_active;
+        if (act == 0) break;
+        if (act <= (3 * last_active) / 4 && c->n_inst > 1) {
+            // drop the tiles of retired channels from the launch
+            rc = refresh_results(c, res);
+            if (rc) break;
+            rc = build_tiles(c, false);
+            if (rc) break;
+            rc = upload_tables(c);
+            if (rc) break;
+            last_active = act;
+        }
+    }
+    double off = -1.0;
+    (void)hipMemcpyAsync(c->d_tol, &off, sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (rc) return rc;
+    rc = refresh_results(c, res);
+    if (rc) return rc;
+    int act = 0;
+    bool bad = false;
+    for (int k = 0; k < c->n_inst; ++k) {
+        if (res[k].retired_at == 0) ++act;
+        if (res[k].bad > 0) bad = true;
+    }
+    if (n_active) *n_active = act;
+    return bad ? LBM_EDIVERGED : LBM_OK;
+}
+
+int lbm_fields(lbm_ctx* c, int32_t inst, double* phi, double* ux, double* uy, double* T, double* p) {
+    if (!c || inst < 0 || inst >= c->n_inst) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    std::vector<Result> res;
+    int rc = refresh_results(c, res);
+    if (rc) return rc;
+    const long long s = inst_steps(c, res[inst]);
+    const lbm_params& P = c->params[inst];
+    const long long n = (long long)P.nx * P.ny;
+    double* out = (double*)dev_alloc(c, sizeof(double) * 5 * n);
+    if (!out) return LBM_ENOMEM;
+    // a one-channel tile table for this launch
+    std::vector<int> tiles;
+    int txs = 0;
+    int nt = tiles_of(P, c->tx, c->ty, &txs);
+    Inst I = c->h_inst[inst];
+    I.tile0 = 0;
+    I.tiles_x = txs;
+    I.ntiles = nt;
+    I.node_off = 0;
+    I.active = 1;
+    Inst* dI = (Inst*)dev_alloc(c, sizeof(Inst));
+    int* dT = (int*)dev_alloc(c, sizeof(int) * nt);
+    if (!dI || !dT) return LBM_ENOMEM;
+    tiles.assign(nt, 0);
+    HIPCHK(c, hipMemcpyAsync(dI, &I, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dT, tiles.data(), sizeof(int) * nt, hipMemcpyHostToDevice, c->stream));
+    StepArgs a;
+    step_args(c, a, (s & 1) != 0);
+    a.insts = dI;
+    a.tile_inst = dT;
+    a.n_tiles = nt;
+    for (int k = 0; k < 5; ++k) a.out[k] = out + (size_t)k * n;
+    hipError_t e = launch_step(c->prec, a, 2, grid_of(nt), c->tx, c->ty, c->stream);
+    if (e != hipSuccess) return fail_hip(c, e, "fields kernel launch");
+    double* dst[5] = {phi, ux, uy, T, p};
+    for (int k = 0; k < 5; ++k)
+        if (dst[k]) HIPCHK(c, hipMemcpyAsync(dst[k], out + (size_t)k * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (void* q : {(void*)dT, (void*)dI, (void*)out}) dev_release(c, q);
+    return LBM_OK;
+}
+
+int lbm_residual(lbm_ctx* c, int32_t inst, double* r, double* sum_phi, double* sum_mass, double* u_int_peak,
+                 int64_t* steps_done) {
+    if (!c || inst < 0 || inst >= c->n_inst) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    std::vector<Result> res;
+    int rc = refresh_results(c, res);
+    if (rc) return rc;
+    const Result& R = res[inst];
+    if (r) *r = R.have_prev ? R.r : INFINITY;
+    if (sum_phi) *sum_phi = R.sum_phi;
+    if (sum_mass) *sum_mass = R.sum_rho;
+    if (u_int_peak) *u_int_peak = R.u_peak;
+    if (steps_done) *steps_done = inst_steps(c, R);
+    return R.bad > 0 ? LBM_EDIVERGED : LBM_OK;
+}
+
+static int state_io(lbm_ctx* c, int32_t inst, double* host, int dir) {
+    if (!c || inst < 0 || inst >= c->n_inst || !host) return LBM_EINVAL;
+    if (dir == 0 && !c->initialised) return LBM_ESTATE;
+    std::vector<Result> res;
+    int rc = refresh_results(c, res);
+    if (rc) return rc;
+    const long long s = c->initialised ? inst_steps(c, res[inst]) : 0;
+    const lbm_params& P = c->params[inst];
+    const long long n = (long long)P.nx * P.ny;
+    double* d = (double*)dev_alloc(c, sizeof(double) * 27 * n);
+    if (!d) return LBM_ENOMEM;
+    StateArgs a;
+    a.insts = c->d_inst;
+    a.inst = inst;
+    a.dir = dir;
+    a.buf_v = (s & 1) ? c->popB : c->popA;
+    a.phi0_v = c->phi0;
+    a.state = d;
+    if (dir == 1) HIPCHK(c, hipMemcpyAsync(d, host, sizeof(double) * 27 * n, hipMemcpyHostToDevice, c->stream));
+    hipError_t e = launch_state(c->prec, a, (int)n, c->stream);
+    if (e != hipSuccess) return fail_hip(c, e, "state kernel launch");
+    if (dir == 0) HIPCHK(c, hipMemcpyAsync(host, d, sizeof(double) * 27 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dev_release(c, d);
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* c, int32_t inst, double* pop) { return state_io(c, inst, pop, 0); }
+
+int lbm_set_state(lbm_ctx* c, int32_t inst, const double* pop) {
+    if (!c || inst < 0 || inst >= c->n_inst || !pop) return LBM_EINVAL;
+    const long long n = 27LL * c->params[inst].nx * c->params[inst].ny;
+    for (long long q = 0; q < n; ++q)
+        if (!std::isfinite(pop[q])) return LBM_EINVAL;
+    if (!c->initialised) {
+        // a context that was never initialised starts at step 0 (cold start
+        // for the other channels) and takes this state for channel inst
+        int rc = lbm_init(c, nullptr);
+        if (rc) return rc;
+    }
+    return state_io(c, inst, const_cast<double*>(pop), 1);
+}
+
+int lbm_profile_steps(lbm_ctx* c, int64_t n, double* ms) {
+    if (!c || n <= 0 || !ms) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int64_t k = 0; k < n; ++k) {
+        StepArgs a;
+        step_args(c, a, (c->steps & 1) != 0);
+        hipError_t e = launch_step(c->prec, a, 0, grid_of(c->n_tiles), c->tx, c->ty, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "step kernel launch");
+        c->steps += 1;
+    }
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / (double)n;
+    // profiled steps record no checks: move the check counter to the step
+    // index of the next check so that later checks report their own step
+    long long next = ((c->steps + CHECK_EVERY - 1) / CHECK_EVERY) * CHECK_EVERY;
+    HIPCHK(c, hipMemcpy(c->d_counter, &next, sizeof(long long), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_info(lbm_ctx* c, int64_t* nodes, int64_t* device_bytes) {
+    if (!c) return LBM_EINVAL;
+    if (nodes) *nodes = c->total_nodes;
+    if (device_bytes) {
+        size_t b = 0;
+        b += 2 * (size_t)c->total_pop * c->elem;
+        b += (size_t)c->total_nodes * 4 * sizeof(double);
+        *device_bytes = (int64_t)b;
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

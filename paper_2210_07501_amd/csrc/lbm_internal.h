@@ -1,0 +1,79 @@
+// lbm_internal.h -- structures shared by the host API and the device code of
+// the HIP library (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Residual, conserved sums and interface peak are recorded every CHECK_EVERY
+// steps (counted from initialisation).
+constexpr int CHECK_EVERY = 100;
+
+// Per-channel descriptor in device memory.
+struct Inst {
+    int nx, ny, tiles_x, tile0;   // tile0: first entry of this channel in the tile table
+    int ntiles, active, pad0, pad1;
+    long long pop_off;            // element offset of the channel in the population buffers
+    long long node_off;           // element offset in node-sized arrays
+    long long row_off;            // offset in the reference-row table (ny + 4 rows)
+    double W, M_phi, w_phi, b;
+    double rho_a, rho_b, mu_a, mu_b, k_a, k_b;
+    double s0, sT, sTT, T_ref;
+    double T_h, dT, T_c, kx;      // kx = 2 pi / l
+    double Fx, Fy;
+    double p_r, T_r;              // storage references of g and h (0 in float64 mode)
+};
+
+struct Result {
+    double r, sum_phi, sum_rho, u_peak, bad;
+    long long check_step, retired_at;
+    int have_prev, pad;
+};
+
+struct StepArgs {
+    const Inst* insts;
+    const int* tile_inst;
+    int n_tiles;
+    const void* src_v;
+    void* dst_v;
+    const void* phi0_v;           // reference rows (compute type)
+    double* snap[4];              // ux, uy, T, phi at the last check
+    double* partials;             // [tile][8]
+    double* out[5];               // fields: phi, ux, uy, T, p
+};
+
+struct FinArgs {
+    Inst* insts;
+    Result* results;
+    const double* partials;
+    double* snap[4];
+    const long long* step_counter;
+    const double* tol;
+};
+
+struct InitArgs {
+    const Inst* insts;
+    void* dst_v;
+    const void* phi0_v;
+    const double* fields[4];      // phi, ux, uy, T (device), when not cold
+    int cold;
+};
+
+struct StateArgs {
+    const Inst* insts;
+    int inst;
+    int dir;                      // 0: buffer -> state, 1: state -> buffer
+    void* buf_v;
+    const void* phi0_v;
+    double* state;                // device [3][9][ny][nx] float64
+};
+
+hipError_t launch_step(int prec, const StepArgs& a, int mode, int grid, int tx, int ty, hipStream_t st);
+hipError_t launch_finalize(const FinArgs& a, int n_inst, hipStream_t st);
+hipError_t launch_counter(long long* c, long long n, hipStream_t st);
+hipError_t launch_count_active(const Inst* insts, int n, int* out, hipStream_t st);
+hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, hipStream_t st);
+hipError_t launch_state(int prec, const StateArgs& a, int nodes, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,825 @@
+// lbm_kernels.hip -- device code of the coupled central-moment LBM step for
+// gfx950 (arXiv 2210.07501, Secs. 3-4, App. B).
+//
+// One workgroup owns a TX x TY tile of lattice nodes of one channel.  The
+// fused step kernel
+//   1. pulls the streamed populations f, g, h of the tile and of a halo ring
+//      (2 nodes for phi, 1 node for T and p*), applying the wall schemes of
+//      Sec. 5 on the fly, and stages phi, T, p* in LDS;
+//   2. fills the ghost rows behind the walls and computes the interface
+//      normal on the tile plus a 1-node ring (isotropic gradients);
+//   3. per node: curvature, surface-tension gradient, pressure force, the
+//      CSF force of Sec. 3, the corrected velocity and pressure of Sec. 4.2,
+//      and the three central-moment collisions of Secs. 4.1-4.3;
+//   4. writes the 27 post-collision populations at the node (pull scheme:
+//      the next step gathers them), coalesced along x.
+// The moment maps P, F(u), F(-u), P^-1 of App. B factor into 1-D maps along
+// x and y on the D2Q9 tensor lattice; they are applied in that factored form
+// and only the central moments that actually relax are formed.
+//
+// Storage: per channel, populations [3][9][ny][nx].  In float32 mode the
+// stored numbers are deviations from rest equilibria w_a X_ref with
+// X_ref = phi0(row) for f (the cold-start tanh profile), p_r for g and T_r
+// for h; phi0 is taken at the row of the node that will pull the value.  In
+// float64 mode all references are zero and the numbers are the populations.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+__device__ __forceinline__ int wrapx(int i, int nx) {
+    return i < 0 ? i + nx : (i >= nx ? i - nx : i);
+}
+__device__ __forceinline__ int modx(int i, int nx) {
+    int r = i % nx;
+    return r < 0 ? r + nx : r;
+}
+
+// D2Q9: index -> (e_x, e_y); weights; opposite; e_y-mirror.
+__device__ __constant__ int c_ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ __constant__ int c_ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <class R> struct W9 {
+    static __device__ __forceinline__ R w(int a) {
+        return a == 0 ? R(4) / R(9) : (a < 5 ? R(1) / R(9) : R(1) / R(36));
+    }
+};
+
+// Parameters of one channel converted to the compute type.
+template <class R> struct P {
+    int nx, ny;
+    R W, M, w_phi, drho, rho_a, mu_a, dmu, k_a, dk;
+    R s0, sT, sTT, dTref;  // dTref = T_r - T_ref
+    R T_h, dT, T_c, kx, Fx, Fy, p_r, T_r;
+    __device__ void load(const Inst& I) {
+        nx = I.nx; ny = I.ny;
+        W = R(I.W); M = R(I.M_phi); w_phi = R(I.w_phi);
+        rho_a = R(I.rho_a); drho = R(I.rho_b - I.rho_a);
+        mu_a = R(I.mu_a); dmu = R(I.mu_b - I.mu_a);
+        k_a = R(I.k_a); dk = R(I.k_b - I.k_a);
+        s0 = R(I.s0); sT = R(I.sT); sTT = R(I.sTT); dTref = R(I.T_r - I.T_ref);
+        T_h = R(I.T_h); dT = R(I.dT); T_c = R(I.T_c); kx = R(I.kx);
+        Fx = R(I.Fx); Fy = R(I.Fy); p_r = R(I.p_r); T_r = R(I.T_r);
+    }
+};
+
+template <class R> __device__ __forceinline__ R T_wall_bottom(const Inst& I, int i) {
+    // T_h + dT cos(2 pi i / l), evaluated in float64
+    return R(I.T_h + I.dT * cos(I.kx * (double)i));
+}
+
+// ---------------------------------------------------------------------------
+// Factored moment maps on the D2Q9 tensor lattice.  Index m[3 * mx + my].
+// Direction of 1-D velocities (0, +1, -1) -> D2Q9 index.
+__device__ __constant__ int c_dir[3][3] = {{0, 2, 4}, {1, 5, 8}, {3, 6, 7}};
+
+// raw moments r[mx][my] = sum_a f_a e_x^mx e_y^my
+template <class R> __device__ __forceinline__ void raw_moments(const R* f, R* r) {
+    R s[3][3];  // s[cx][my]
+#pragma unroll
+    for (int cx = 0; cx < 3; ++cx) {
+        R f0 = f[c_dir[cx][0]], fp = f[c_dir[cx][1]], fm = f[c_dir[cx][2]];
+        s[cx][0] = f0 + fp + fm;
+        s[cx][1] = fp - fm;
+        s[cx][2] = fp + fm;
+    }
+#pragma unroll
+    for (int my = 0; my < 3; ++my) {
+        r[0 * 3 + my] = s[0][my] + s[1][my] + s[2][my];
+        r[1 * 3 + my] = s[1][my] - s[2][my];
+        r[2 * 3 + my] = s[1][my] + s[2][my];
+    }
+}
+
+// raw moments from central moments (F(-u)): (e - u + u)^m binomially
+template <class R> __device__ __forceinline__ void central_to_raw(R* c, R ux, R uy) {
+#pragma unroll
+    for (int mx = 0; mx < 3; ++mx) {
+        R c0 = c[mx * 3 + 0], c1 = c[mx * 3 + 1], c2 = c[mx * 3 + 2];
+        c[mx * 3 + 1] = c1 + uy * c0;
+        c[mx * 3 + 2] = c2 + R(2) * uy * c1 + uy * uy * c0;
+    }
+#pragma unroll
+    for (int my = 0; my < 3; ++my) {
+        R c0 = c[0 * 3 + my], c1 = c[1 * 3 + my], c2 = c[2 * 3 + my];
+        c[1 * 3 + my] = c1 + ux * c0;
+        c[2 * 3 + my] = c2 + R(2) * ux * c1 + ux * ux * c0;
+    }
+}
+
+// distributions from raw moments (P^-1), 1-D inverse along y then x
+template <class R> __device__ __forceinline__ void raw_to_dist(const R* r, R* f) {
+    R s[3][3];  // s[cx][my]
+#pragma unroll
+    for (int my = 0; my < 3; ++my) {
+        R r0 = r[0 * 3 + my], r1 = r[1 * 3 + my], r2 = r[2 * 3 + my];
+        s[0][my] = r0 - r2;
+        s[1][my] = R(0.5) * (r1 + r2);
+        s[2][my] = R(0.5) * (r2 - r1);
+    }
+#pragma unroll
+    for (int cx = 0; cx < 3; ++cx) {
+        f[c_dir[cx][0]] = s[cx][0] - s[cx][2];
+        f[c_dir[cx][1]] = R(0.5) * (s[cx][1] + s[cx][2]);
+        f[c_dir[cx][2]] = R(0.5) * (s[cx][2] - s[cx][1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Populations: buffer layout [3][9][ny][nx] per channel.
+template <class S> struct Pop {
+    S* base;
+    int nx, ny;
+    __device__ __forceinline__ size_t idx(int d, int a, int j, int i) const {
+        return (((size_t)(d * 9 + a) * (size_t)ny + (size_t)j) * (size_t)nx + (size_t)i);
+    }
+};
+
+// Gather the streamed populations of node (i, j) (0 <= j < ny) from the
+// post-collision buffer, with the wall schemes of Sec. 5: g half-way
+// bounce-back, h anti-bounce-back to the wall temperature, f specular
+// (free-slip).  Returned as deviations relative to row j's references.
+// NEED: bit 0 f, bit 1 g, bit 2 h.
+template <class S, class R, int NEED>
+__device__ __forceinline__ void pull_node(const Pop<S>& src, const Inst& I, const P<R>& p, int i,
+                                          int j, R* f, R* g, R* h) {
+    const int nx = p.nx, ny = p.ny;
+    const int im = wrapx(i - 1, nx), ip = wrapx(i + 1, nx);
+    // rows j (e_y = 0), j - 1 (e_y = +1), j + 1 (e_y = -1)
+    const bool has_s = j > 0, has_n = j < ny - 1;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const int ex = c_ex[a], ey = c_ey[a];
+        const int is = ex == 0 ? i : (ex > 0 ? im : ip);
+        const bool interior = ey == 0 || (ey > 0 ? has_s : has_n);
+        if (interior) {
+            const int js = j - ey;
+            if (NEED & 1) f[a] = R(src.base[src.idx(0, a, js, is)]);
+            if (NEED & 2) g[a] = R(src.base[src.idx(1, a, js, is)]);
+            if (NEED & 4) h[a] = R(src.base[src.idx(2, a, js, is)]);
+        } else {
+            // mirror_y(a) and opposite(a) for the 6 directions with e_y != 0
+            const int mir = (a == 2) ? 4 : (a == 4) ? 2 : (a == 5) ? 8 : (a == 8) ? 5 : (a == 6) ? 7 : 6;
+            const int opp = (a == 2) ? 4 : (a == 4) ? 2 : (a == 5) ? 7 : (a == 7) ? 5 : (a == 6) ? 8 : 6;
+            if (NEED & 1) f[a] = R(src.base[src.idx(0, mir, j, is)]);
+            if (NEED & 2) g[a] = R(src.base[src.idx(1, opp, j, i)]);
+            if (NEED & 4) {
+                const R Tw = (ey > 0) ? T_wall_bottom<R>(I, i) : p.T_c;
+                h[a] = -R(src.base[src.idx(2, opp, j, i)]) + R(2) * W9<R>::w(a) * (Tw - p.T_r);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of NV doubles (wavefront shuffles + LDS), fixed order.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum(double* v, double* red /* LDS [NT/64][NV] */) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        v[k] = x;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wv * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
+            v[k] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused step kernel.
+// MODE 0: step; 1: step + residual snapshot; 2: fields only (no step).
+template <int TX, int TY, class S, class R, bool DEV, int MODE>
+__global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
+    constexpr int NT = TX * TY;
+    constexpr int LX2 = TX + 4, LY2 = TY + 4;   // phi region (halo 2)
+    constexpr int LX1 = TX + 2, LY1 = TY + 2;   // T, p*, n region (halo 1)
+    constexpr int RING = LX2 * LY2 - TX * TY;
+
+    __shared__ R s_phb[LY2 * LX2];
+    __shared__ R s_Tb[LY1 * LX1];
+    __shared__ R s_pb[LY1 * LX1];
+    __shared__ R s_nx[LY1 * LX1];
+    __shared__ R s_dny[LY1 * LX1];
+    __shared__ R s_phi0[LY2];     // reference phi0 of rows y0-2 .. y0+TY+1
+    __shared__ R s_n0y[LY1];      // reference normal of rows y0-1 .. y0+TY
+    __shared__ double s_red[(NT / 64) * 8];
+
+    // XCD-aware mapping: consecutive tiles share an XCD (and its L2)
+    const int G = gridDim.x, per = G >> 3;
+    const int tile = (per > 0) ? ((blockIdx.x & 7) * per + (blockIdx.x >> 3)) : blockIdx.x;
+    if (tile >= a.n_tiles) return;
+    const int inst = a.tile_inst[tile];
+    const Inst& I = a.insts[inst];
+    if (MODE != 2 && !I.active) return;
+    P<R> p;
+    p.load(I);
+    const int nx = p.nx, ny = p.ny;
+    const int lt = tile - I.tile0;
+    const int x0 = (lt % I.tiles_x) * TX, y0 = (lt / I.tiles_x) * TY;
+
+    const R* phi0t = (const R*)a.phi0_v;
+    Pop<S> src{(S*)a.src_v + I.pop_off, nx, ny};
+    const int tid = threadIdx.x;
+
+    // reference rows
+    for (int k = tid; k < LY2; k += NT) {
+        const int gj = y0 - 2 + k;
+        s_phi0[k] = DEV ? phi0t[I.row_off + min(max(gj, -2), ny + 1) + 2] : R(0);
+    }
+    __syncthreads();
+    for (int k = tid; k < LY1; k += NT) {
+        // reference normal: sign of the reference y-gradient (0 where it vanishes)
+        R g0 = R(0.5) * (s_phi0[k + 2] - s_phi0[k]);
+        R eps = sizeof(R) == 8 ? R(1e-12) : R(1e-6);
+        s_n0y[k] = DEV ? (g0 > eps ? R(1) : (g0 < -eps ? R(-1) : R(0))) : R(0);
+    }
+
+    // ---- phase 1: pull own node (27 values kept) and the halo ring --------
+    const int tx = tid % TX, ty = tid / TX;
+    const int gi = modx(x0 + tx, nx), gj = y0 + ty;
+    const bool own_row = gj < ny;
+    const bool own_ok = own_row && (x0 + tx < nx);
+    R f[9], g[9], h[9];
+    R rf[9], rg[9], rh[9];
+    if (own_row) {
+        pull_node<S, R, 7>(src, I, p, gi, gj, f, g, h);
+        raw_moments(f, rf);
+        raw_moments(g, rg);
+        raw_moments(h, rh);
+        s_phb[(ty + 2) * LX2 + tx + 2] = rf[0];
+        s_pb[(ty + 1) * LX1 + tx + 1] = rg[0];
+        s_Tb[(ty + 1) * LX1 + tx + 1] = rh[0];
+    }
+    for (int k = tid; k < RING; k += NT) {
+        int hx, hy;
+        if (k < 2 * LX2) { hy = -2 + k / LX2; hx = -2 + k % LX2; }
+        else if (k < 4 * LX2) { int q = k - 2 * LX2; hy = TY + q / LX2; hx = -2 + q % LX2; }
+        else { int q = k - 4 * LX2; hy = q / 4; int c = q % 4; hx = c < 2 ? c - 2 : TX + c - 2; }
+        const int jj = y0 + hy;
+        if (jj < 0 || jj >= ny) continue;
+        const int ii = modx(x0 + hx, nx);
+        const bool h1 = hx >= -1 && hx <= TX && hy >= -1 && hy <= TY;
+        R tf[9], tg[9], th[9];
+        if (h1) {
+            pull_node<S, R, 7>(src, I, p, ii, jj, tf, tg, th);
+            R s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) { s1 += tf[q]; s2 += tg[q]; s3 += th[q]; }
+            s_phb[(hy + 2) * LX2 + hx + 2] = s1;
+            s_pb[(hy + 1) * LX1 + hx + 1] = s2;
+            s_Tb[(hy + 1) * LX1 + hx + 1] = s3;
+        } else {
+            pull_node<S, R, 1>(src, I, p, ii, jj, tf, tg, th);
+            R s1 = 0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) s1 += tf[q];
+            s_phb[(hy + 2) * LX2 + hx + 2] = s1;
+        }
+    }
+    __syncthreads();
+
+    // ---- ghost rows: phi, p* mirrored, T = 2 T_w - T ------------------------
+    for (int k = tid; k < LY2 * LX2; k += NT) {
+        const int hy = k / LX2 - 2, hx = k % LX2 - 2;
+        const int jj = y0 + hy;
+        if (jj >= 0 && jj < ny) continue;
+        const int mj = jj < 0 ? -1 - jj : 2 * ny - 1 - jj;      // mirror row
+        const int mhy = mj - y0;
+        const bool valid = (jj >= -2 && jj <= ny + 1) && mhy >= -2 && mhy <= TY + 1;
+        R v = R(0);
+        if (valid) {
+            v = s_phb[(mhy + 2) * LX2 + hx + 2] + (s_phi0[mhy + 2] - s_phi0[hy + 2]);
+        }
+        s_phb[(hy + 2) * LX2 + hx + 2] = v;
+        if (hx >= -1 && hx <= TX && hy >= -1 && hy <= TY) {
+            R vp = R(0), vT = R(0);
+            if (valid && (jj == -1 || jj == ny)) {
+                vp = s_pb[(mhy + 1) * LX1 + hx + 1];
+                const R Tm = s_Tb[(mhy + 1) * LX1 + hx + 1];
+                const int ii = modx(x0 + hx, nx);
+                const R Tw = (jj < 0) ? T_wall_bottom<R>(I, ii) : p.T_c;
+                vT = R(2) * (Tw - p.T_r) - Tm;
+            }
+            s_pb[(hy + 1) * LX1 + hx + 1] = vp;
+            s_Tb[(hy + 1) * LX1 + hx + 1] = vT;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: interface normal on the tile + 1 ring ----------------------
+    const R eps_n = sizeof(R) == 8 ? R(1e-12) : R(1e-6);
+    for (int k = tid; k < LY1 * LX1; k += NT) {
+        const int hy = k / LX1 - 1, hx = k % LX1 - 1;
+        const int jj = y0 + hy;
+        R nxv = R(0), dny = R(0);
+        if (jj >= -1 && jj <= ny) {
+            const R* c = &s_phb[(hy + 2) * LX2 + hx + 2];
+            const R E = c[1], Wv = c[-1], N = c[LX2], Sv = c[-LX2];
+            const R NE = c[LX2 + 1], NW = c[LX2 - 1], SE = c[-LX2 + 1], SW = c[-LX2 - 1];
+            const R Gx = (E - Wv) * (R(1) / R(3)) + (NE - NW + SE - SW) * (R(1) / R(12));
+            const R G0y = R(0.5) * (s_phi0[hy + 3] - s_phi0[hy + 1]);
+            const R Gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12)) + G0y;
+            const R mag = sqrt(Gx * Gx + Gy * Gy);
+            const R n0 = s_n0y[hy + 1];
+            if (mag > eps_n) {
+                nxv = Gx / mag;
+                if (n0 != R(0) && ((Gy > R(0)) == (n0 > R(0)))) {
+                    // n_y - n0 without cancellation: -Gx^2 / ((Gy + n0 |G|) |G|)
+                    dny = -(Gx * Gx) / ((Gy + n0 * mag) * mag);
+                } else {
+                    dny = Gy / mag - n0;
+                }
+            } else {
+                nxv = R(0);
+                dny = -n0;
+            }
+        }
+        s_nx[k] = nxv;
+        s_dny[k] = dny;
+    }
+    __syncthreads();
+
+    // ---- phase 3: forces, velocity, collisions -------------------------------
+    double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (own_row) {
+        const R cs2 = R(1) / R(3);
+        const int c2 = (ty + 2) * LX2 + tx + 2, c1 = (ty + 1) * LX1 + tx + 1;
+        // isotropic gradient helper on an LDS array with row stride L
+        auto grad = [&](const R* arr, int c, int L, R& gx, R& gy) {
+            const R E = arr[c + 1], Wv = arr[c - 1], N = arr[c + L], Sv = arr[c - L];
+            const R NE = arr[c + L + 1], NW = arr[c + L - 1], SE = arr[c - L + 1], SW = arr[c - L - 1];
+            gx = (E - Wv) * (R(1) / R(3)) + (NE - NW + SE - SW) * (R(1) / R(12));
+            gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12));
+        };
+        R Gx, Gy;
+        grad(s_phb, c2, LX2, Gx, Gy);
+        Gy += R(0.5) * (s_phi0[ty + 3] - s_phi0[ty + 1]);
+        const R g2 = Gx * Gx + Gy * Gy;
+        const R nxv = s_nx[c1];
+        const R nyv = s_n0y[ty + 1] + s_dny[c1];
+        R dnx_dx, dnx_dy, ddy_dx, ddy_dy;
+        grad(s_nx, c1, LX1, dnx_dx, dnx_dy);
+        grad(s_dny, c1, LX1, ddy_dx, ddy_dy);
+        const R curv = dnx_dx + ddy_dy + R(0.5) * (s_n0y[ty + 2] - s_n0y[ty]);
+        // surface tension from the stencil temperatures (Eq. ST_SRF), less sigma0
+        R sg[9];
+        {
+            const int offs[9] = {0, 1, LX1, -1, -LX1, LX1 + 1, LX1 - 1, -LX1 - 1, -LX1 + 1};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const R d = s_Tb[c1 + offs[q]] + p.dTref;
+                sg[q] = (p.sT + p.sTT * d) * d;
+            }
+        }
+        const R dsx = (sg[1] - sg[3]) * (R(1) / R(3)) + (sg[5] - sg[6] + sg[8] - sg[7]) * (R(1) / R(12));
+        const R dsy = (sg[2] - sg[4]) * (R(1) / R(3)) + (sg[5] + sg[6] - sg[8] - sg[7]) * (R(1) / R(12));
+        const R sig = p.s0 + sg[0];
+        R dpx, dpy;
+        grad(s_pb, c1, LX1, dpx, dpy);
+        // CSF force (Sec. 3): 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
+        const R dl = R(1.5) * p.W * g2;
+        const R Fsx = dl * (-sig * curv * nxv + (R(1) - nxv * nxv) * dsx - nxv * nyv * dsy);
+        const R Fsy = dl * (-sig * curv * nyv + (R(1) - nyv * nyv) * dsy - nxv * nyv * dsx);
+        const R Ftx = Fsx + p.Fx, Fty = Fsy + p.Fy;
+        // pressure force F_p = -grad(p* - rho c_s^2), rho linear in phi
+        const R Fpx = -dpx + cs2 * p.drho * Gx;
+        const R Fpy = -dpy + cs2 * p.drho * Gy;
+        // macroscopic update (Sec. 4.2)
+        const R phb = rf[0];
+        const R phi = s_phi0[ty + 2] + phb;
+        const R rho = p.rho_a + phi * p.drho;
+        const R ux = (rg[3] + R(0.5) * cs2 * Ftx) / (rho * cs2);
+        const R uy = (rg[1] + R(0.5) * cs2 * Fty) / (rho * cs2);
+        const R Gam = Fpx * ux + Fpy * uy;
+        const R pb = rg[0] + R(0.5) * Gam;          // p - p_r
+        const R Tb = rh[0];                          // T - T_r
+
+        if (MODE == 2) {
+            if (own_ok) {
+                const size_t q = (size_t)I.node_off + (size_t)gj * nx + gi;
+                a.out[0][q] = (double)phi;
+                a.out[1][q] = (double)ux;
+                a.out[2][q] = (double)uy;
+                a.out[3][q] = (double)p.T_r + (double)Tb;
+                a.out[4][q] = (double)p.p_r + (double)pb;
+            }
+        } else {
+            if (MODE == 1 && own_ok) {
+                const size_t q = (size_t)I.node_off + (size_t)gj * nx + gi;
+                const double dux = (double)ux, duy = (double)uy;
+                const double dT = (double)Tb + (double)p.dTref;   // T - T_ref
+                const double Tfull = (double)p.T_r + (double)Tb;
+                const double o_ux = a.snap[0][q], o_uy = a.snap[1][q], o_T = a.snap[2][q];
+                red[0] = (dux - o_ux) * (dux - o_ux) + (duy - o_uy) * (duy - o_uy);
+                red[1] = dux * dux + duy * duy;
+                red[2] = (Tfull - o_T) * (Tfull - o_T);
+                red[3] = dT * dT;
+                red[4] = (double)phi;
+                red[5] = (double)rho;
+                const bool bad = !(isfinite(dux) && isfinite(duy) && isfinite(Tfull) && isfinite((double)phi) &&
+                                   isfinite((double)pb));
+                red[6] = bad ? 1.0 : 0.0;
+                a.snap[0][q] = dux;
+                a.snap[1][q] = duy;
+                a.snap[2][q] = Tfull;
+                a.snap[3][q] = (double)phi;
+            }
+            // local relaxation rates
+            const R mu = p.mu_a + phi * p.dmu, kc = p.k_a + phi * p.dk;
+            const R w_nu = R(1) / (R(3) * (mu / rho) + R(0.5));
+            const R w_T = R(1) / (R(3) * (kc / rho) + R(0.5));
+            const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+
+            // --- ACE (Sec. 4.1): relax first central moments to M theta n ---
+            {
+                const R ph0 = s_phi0[ty + 2];
+                const R theta = R(4) * phi * (R(1) - phi) / p.W;
+                const R k10 = rf[3] - ux * phi, k01 = rf[1] - uy * phi;
+                const R t10 = k10 + p.w_phi * (p.M * theta * nxv - k10);
+                const R t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
+                // post-collision central moments minus ph0 * (rest central moments)
+                R c[9];
+                c[0] = phb;                                  // 00
+                c[1] = t01 + ph0 * uy;                       // 01
+                c[2] = phb * cs2 - ph0 * uy2;                // 02
+                c[3] = t10 + ph0 * ux;                       // 10
+                c[4] = -ph0 * uxy;                           // 11
+                c[5] = ph0 * ux * (cs2 + uy2);               // 12
+                c[6] = phb * cs2 - ph0 * ux2;                // 20
+                c[7] = ph0 * uy * (cs2 + ux2);               // 21
+                c[8] = phb * (cs2 * cs2) - ph0 * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
+                central_to_raw(c, ux, uy);
+                raw_to_dist(c, f);
+            }
+            // --- energy (Sec. 4.3) ---
+            {
+                const R Tr = p.T_r;
+                const R c10 = rh[3] - ux * (Tr + Tb), c01 = rh[1] - uy * (Tr + Tb);
+                R c[9];
+                c[0] = Tb;
+                c[1] = c01 * (R(1) - w_T) + Tr * uy;
+                c[2] = Tb * cs2 - Tr * uy2;
+                c[3] = c10 * (R(1) - w_T) + Tr * ux;
+                c[4] = -Tr * uxy;
+                c[5] = Tr * ux * (cs2 + uy2);
+                c[6] = Tb * cs2 - Tr * ux2;
+                c[7] = Tr * uy * (cs2 + ux2);
+                c[8] = Tb * (cs2 * cs2) - Tr * (cs2 * (ux2 + uy2) + ux2 * uy2);
+                central_to_raw(c, ux, uy);
+                raw_to_dist(c, h);
+            }
+            // --- hydrodynamics (Sec. 4.2) ---
+            {
+                const R pr = p.p_r;
+                const R vphi = pb + (pr - rho * cs2);     // p - rho c_s^2
+                const R P0 = rg[0] + pr;                  // sum g (full)
+                // pre-collision central moments that relax at omega_nu
+                const R e2d = (rg[6] - rg[2]) - R(2) * ux * rg[3] + R(2) * uy * rg[1] + (ux2 - uy2) * P0;
+                const R e11 = rg[4] - uy * rg[3] - ux * rg[1] + uxy * P0;
+                // sources (Sec. 4.2)
+                const R s10 = cs2 * Ftx - ux * Gam, s01 = cs2 * Fty - uy * Gam;
+                const R s20 = R(2) * cs2 * Fpx * ux + (ux2 + cs2) * Gam;
+                const R s02 = R(2) * cs2 * Fpy * uy + (uy2 + cs2) * Gam;
+                const R s11 = cs2 * (Fpx * uy + Fpy * ux) + uxy * Gam;
+                // equilibria (deviation parts computed below)
+                const R q2d = vphi * (ux2 - uy2), q11 = vphi * uxy;
+                const R t2d = e2d + w_nu * (q2d - e2d) + (R(1) - R(0.5) * w_nu) * (s20 - s02);
+                const R t11 = e11 + w_nu * (q11 - e11) + (R(1) - R(0.5) * w_nu) * s11;
+                // trace: 2 p c_s^2 + vphi u^2 + s_2s / 2, minus p_r (2 c_s^2 + u^2)
+                const R t2s_dev = R(2) * cs2 * pb + (vphi - pr) * (ux2 + uy2) + R(0.5) * (s20 + s02);
+                const R t2d_dev = t2d - pr * (ux2 - uy2);
+                const R pv = pr - vphi;                   // p_r - (p - rho c_s^2)
+                R c[9];
+                c[0] = pb + R(0.5) * Gam;                           // 00
+                c[1] = pv * uy + R(0.5) * s01;                      // 01
+                c[2] = R(0.5) * (t2s_dev - t2d_dev);                // 02
+                c[3] = pv * ux + R(0.5) * s10;                      // 10
+                c[4] = t11 - pr * uxy;                              // 11
+                c[5] = pv * (uy2 + cs2) * ux;                       // 12
+                c[6] = R(0.5) * (t2s_dev + t2d_dev);                // 20
+                c[7] = pv * (ux2 + cs2) * uy;                       // 21
+                c[8] = pb * (cs2 * cs2) + (pb - rho * cs2) * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
+                central_to_raw(c, ux, uy);
+                raw_to_dist(c, g);
+            }
+            if (own_ok) {
+                Pop<S> dst{(S*)a.dst_v + I.pop_off, nx, ny};
+                if (DEV) {
+                    // f deviations relative to the row of the node that pulls them
+                    const R ph0 = s_phi0[ty + 2];
+#pragma unroll
+                    for (int q = 1; q < 9; ++q) {
+                        const int ey = c_ey[q];
+                        if (ey == 0) continue;
+                        const int jr = gj + ey;
+                        const R phr = (jr >= 0 && jr < ny) ? s_phi0[ty + 2 + ey] : ph0;
+                        f[q] += W9<R>::w(q) * (ph0 - phr);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    dst.base[dst.idx(0, q, gj, gi)] = S(f[q]);
+                    dst.base[dst.idx(1, q, gj, gi)] = S(g[q]);
+                    dst.base[dst.idx(2, q, gj, gi)] = S(h[q]);
+                }
+            }
+        }
+    }
+    if (MODE == 1) {
+        block_sum<NT, 8>(red, s_red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a.partials[(size_t)tile * 8 + k] = red[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance check: fixed-order sum of block partials, residual, interface
+// velocity peak on the phi = 1/2 level, retirement.
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+    __shared__ double s_red[4 * 8];
+    const int inst = blockIdx.x;
+    Inst& I = a.insts[inst];
+    Result& res = a.results[inst];
+    if (!I.active) return;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < I.ntiles; t += 256) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] += a.partials[(size_t)(I.tile0 + t) * 8 + k];
+    }
+    block_sum<256, 8>(v, s_red);
+    __syncthreads();
+    // interface peak from the snapshot (ux at index 0, phi at index 3)
+    double peak = 0.0;
+    const int nx = I.nx, ny = I.ny;
+    const double* ux = a.snap[0] + I.node_off;
+    const double* ph = a.snap[3] + I.node_off;
+    int jstart = (int)I.b - 1;
+    jstart = jstart < 0 ? 0 : (jstart > ny - 2 ? ny - 2 : jstart);
+    for (int i = threadIdx.x; i < nx; i += 256) {
+        double u = 0.0;
+        bool found = false;
+        for (int d = 0; d < ny && !found; ++d) {
+            for (int sgn = 0; sgn < 2 && !found; ++sgn) {
+                const int j = sgn ? jstart - d : jstart + d;
+                if ((sgn && d == 0) || j < 0 || j > ny - 2) continue;
+                const double c0 = ph[(size_t)j * nx + i] - 0.5, c1 = ph[(size_t)(j + 1) * nx + i] - 0.5;
+                if (c0 >= 0.0 && c1 < 0.0) {
+                    const double t = c0 / (c0 - c1);
+                    u = (1.0 - t) * ux[(size_t)j * nx + i] + t * ux[(size_t)(j + 1) * nx + i];
+                    found = true;
+                }
+            }
+        }
+        peak = fmax(peak, fabs(u));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) peak = fmax(peak, __shfl_xor(peak, o, 64));
+    __shared__ double s_pk[4];
+    if ((threadIdx.x & 63) == 0) s_pk[threadIdx.x >> 6] = peak;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        peak = fmax(fmax(s_pk[0], s_pk[1]), fmax(s_pk[2], s_pk[3]));
+        const double K = (double)CHECK_EVERY;
+        double r = INFINITY;
+        if (res.have_prev) {
+            const double ru = v[1] > 0 ? sqrt(v[0]) / sqrt(v[1]) : (v[0] == 0 ? 0.0 : INFINITY);
+            const double rT = v[3] > 0 ? sqrt(v[2]) / sqrt(v[3]) : (v[2] == 0 ? 0.0 : INFINITY);
+            r = fmax(ru, rT) / K;
+        }
+        res.r = r;
+        res.sum_phi = v[4];
+        res.sum_rho = v[5];
+        res.u_peak = peak;
+        res.bad = v[6];
+        res.have_prev = 1;
+        res.check_step = *a.step_counter;
+        const double tol = *a.tol;
+        if (v[6] > 0.0) {
+            I.active = 0;
+            res.retired_at = *a.step_counter + 1;
+        } else if (tol > 0.0 && r <= tol) {
+            I.active = 0;
+            res.retired_at = *a.step_counter + 1;
+        }
+    }
+}
+
+// advance the device step counter by n (one thread)
+__global__ void counter_kernel(long long* c, long long n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c += n;
+}
+
+__global__ void count_active_kernel(const Inst* insts, int n, int* out) {
+    __shared__ int s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    int c = 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) c += insts[k].active ? 1 : 0;
+    atomicAdd(&s, c);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium state from fields, written into the post-collision buffer so
+// that the next gather yields it (inverse of the gather, walls included).
+template <class S, class R, bool DEV>
+__global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
+    const int inst = blockIdx.y;
+    const Inst& I = a.insts[inst];
+    const int nx = I.nx, ny = I.ny;
+    const long long n = (long long)nx * ny;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % nx), j = (int)(q / nx);
+    const double cs2 = 1.0 / 3.0;
+    double phi, ux, uy, T;
+    if (a.cold) {
+        // fluid at rest, tanh interface at y = b - 1/2, T linear between walls
+        phi = 0.5 * (1.0 + tanh(2.0 * ((I.b - 0.5) - (double)j) / I.W));
+        ux = 0.0;
+        uy = 0.0;
+        const double Tb = I.T_h + I.dT * cos(I.kx * (double)i);
+        T = Tb + (I.T_c - Tb) * ((double)j + 0.5) / (double)ny;
+    } else {
+        const size_t o = (size_t)I.node_off + (size_t)q;
+        phi = a.fields[0][o];
+        ux = a.fields[1][o];
+        uy = a.fields[2][o];
+        T = a.fields[3][o];
+    }
+    const double rho = I.rho_a + phi * (I.rho_b - I.rho_a);
+    const double p0 = 1.0 / 3.0;
+    const double vphi = p0 - rho * cs2;
+    const double ux2 = ux * ux, uy2 = uy * uy;
+    // central-moment equilibria; reference rest moments subtracted (DEV)
+    const double ph0 = DEV ? (double)((const R*)a.phi0_v)[I.row_off + j + 2] : 0.0;
+    const double pr = DEV ? I.p_r : 0.0, Tr = DEV ? I.T_r : 0.0;
+    double cf[9], cg[9], ch[9];
+    // order [mx*3+my]
+    auto rest_central = [&](double X, double* c, double sc) {
+        // add sc * X * (central moments about u of the rest equilibrium)
+        c[0] += sc * X;
+        c[1] += sc * X * (-uy);
+        c[2] += sc * X * (cs2 + uy2);
+        c[3] += sc * X * (-ux);
+        c[4] += sc * X * (ux * uy);
+        c[5] += sc * X * (-ux * (cs2 + uy2));
+        c[6] += sc * X * (cs2 + ux2);
+        c[7] += sc * X * (-uy * (cs2 + ux2));
+        c[8] += sc * X * (cs2 + ux2) * (cs2 + uy2);
+    };
+    for (int k = 0; k < 9; ++k) { cf[k] = 0; cg[k] = 0; ch[k] = 0; }
+    cf[0] = phi; cf[2] = cs2 * phi; cf[6] = cs2 * phi; cf[8] = cs2 * cs2 * phi;
+    ch[0] = T; ch[2] = cs2 * T; ch[6] = cs2 * T; ch[8] = cs2 * cs2 * T;
+    cg[0] = p0; cg[3] = -vphi * ux; cg[1] = -vphi * uy;
+    cg[6] = p0 * cs2 + vphi * ux2; cg[2] = p0 * cs2 + vphi * uy2; cg[4] = vphi * ux * uy;
+    cg[7] = -vphi * (ux2 + cs2) * uy; cg[5] = -vphi * (uy2 + cs2) * ux;
+    cg[8] = cs2 * cs2 * cs2 * rho + vphi * (ux2 + cs2) * (uy2 + cs2);
+    rest_central(ph0, cf, -1.0);
+    rest_central(pr, cg, -1.0);
+    rest_central(Tr, ch, -1.0);
+    double ef[9], eg[9], eh[9];
+    central_to_raw(cf, ux, uy); raw_to_dist(cf, ef);
+    central_to_raw(cg, ux, uy); raw_to_dist(cg, eg);
+    central_to_raw(ch, ux, uy); raw_to_dist(ch, eh);
+    Pop<S> dst{(S*)a.dst_v + I.pop_off, nx, ny};
+    // inverse gather: the value that node (i, j) will pull for direction k
+    for (int k = 0; k < 9; ++k) {
+        const int ex = c_ex[k], ey = c_ey[k];
+        const int js = j - ey;
+        const int is = wrapx(i - ex, nx);
+        const double w = W9<double>::w(k);
+        if (js >= 0 && js < ny) {
+            dst.base[dst.idx(0, k, js, is)] = S(ef[k]);
+            dst.base[dst.idx(1, k, js, is)] = S(eg[k]);
+            dst.base[dst.idx(2, k, js, is)] = S(eh[k]);
+        } else {
+            const int mir = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 8 : (k == 8) ? 5 : (k == 6) ? 7 : 6;
+            const int opp = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 7 : (k == 7) ? 5 : (k == 6) ? 8 : 6;
+            const double Tw = (ey > 0) ? I.T_h + I.dT * cos(I.kx * (double)i) : I.T_c;
+            dst.base[dst.idx(0, mir, j, is)] = S(ef[k]);
+            dst.base[dst.idx(1, opp, j, i)] = S(eg[k]);
+            dst.base[dst.idx(2, opp, j, i)] = S(2.0 * w * (Tw - Tr) - eh[k]);
+        }
+    }
+}
+
+// Populations (absolute, float64) of one instance <-> post-collision buffer.
+// dir 0: buffer -> state (gather), dir 1: state -> buffer (inverse gather).
+template <class S, bool DEV>
+__global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
+    const Inst& I = a.insts[a.inst];
+    const int nx = I.nx, ny = I.ny;
+    const long long n = (long long)nx * ny;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % nx), j = (int)(q / nx);
+    const double ph0 = DEV ? (double)((const float*)a.phi0_v)[I.row_off + j + 2] : 0.0;
+    const double pr = DEV ? I.p_r : 0.0, Tr = DEV ? I.T_r : 0.0;
+    Pop<S> buf{(S*)a.buf_v + I.pop_off, nx, ny};
+    for (int k = 0; k < 9; ++k) {
+        const int ex = c_ex[k], ey = c_ey[k];
+        const int js = j - ey;
+        const int is = wrapx(i - ex, nx);
+        const double w = W9<double>::w(k);
+        size_t kf, kg, kh;
+        double sgn_h = 1.0, add_h = 0.0;
+        if (js >= 0 && js < ny) {
+            kf = buf.idx(0, k, js, is); kg = buf.idx(1, k, js, is); kh = buf.idx(2, k, js, is);
+        } else {
+            const int mir = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 8 : (k == 8) ? 5 : (k == 6) ? 7 : 6;
+            const int opp = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 7 : (k == 7) ? 5 : (k == 6) ? 8 : 6;
+            const double Tw = (ey > 0) ? I.T_h + I.dT * cos(I.kx * (double)i) : I.T_c;
+            kf = buf.idx(0, mir, j, is); kg = buf.idx(1, opp, j, i); kh = buf.idx(2, opp, j, i);
+            sgn_h = -1.0;
+            add_h = 2.0 * w * (Tw - Tr);
+        }
+        const size_t o0 = ((size_t)(0 * 9 + k) * ny + j) * nx + i;
+        const size_t o1 = ((size_t)(1 * 9 + k) * ny + j) * nx + i;
+        const size_t o2 = ((size_t)(2 * 9 + k) * ny + j) * nx + i;
+        if (a.dir == 0) {
+            a.state[o0] = w * ph0 + (double)buf.base[kf];
+            a.state[o1] = w * pr + (double)buf.base[kg];
+            a.state[o2] = w * Tr + sgn_h * (double)buf.base[kh] + add_h;
+        } else {
+            buf.base[kf] = S(a.state[o0] - w * ph0);
+            buf.base[kg] = S(a.state[o1] - w * pr);
+            // sgn_h * stored + add_h = state - w Tr  ->  stored = sgn_h (state - w Tr - add_h)
+            buf.base[kh] = S(sgn_h * (a.state[o2] - w * Tr - add_h));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (instantiations).
+template <int TX, int TY, class S, class R, bool DEV>
+static hipError_t launch_step_t(const StepArgs& a, int mode, int grid, hipStream_t st) {
+    dim3 g(grid), b(TX * TY);
+    if (mode == 0) hipLaunchKernelGGL((step_kernel<TX, TY, S, R, DEV, 0>), g, b, 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((step_kernel<TX, TY, S, R, DEV, 1>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((step_kernel<TX, TY, S, R, DEV, 2>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+template <class S, class R, bool DEV>
+static hipError_t launch_step_p(const StepArgs& a, int mode, int grid, int tx, int ty, hipStream_t st) {
+    if (tx == 32 && ty == 8) return launch_step_t<32, 8, S, R, DEV>(a, mode, grid, st);
+    if (tx == 64 && ty == 4) return launch_step_t<64, 4, S, R, DEV>(a, mode, grid, st);
+    if (tx == 16 && ty == 16) return launch_step_t<16, 16, S, R, DEV>(a, mode, grid, st);
+    if (tx == 64 && ty == 8) return launch_step_t<64, 8, S, R, DEV>(a, mode, grid, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int prec, const StepArgs& a, int mode, int grid, int tx, int ty, hipStream_t st) {
+    if (prec == 0) return launch_step_p<double, double, false>(a, mode, grid, tx, ty, st);
+    return launch_step_p<float, float, true>(a, mode, grid, tx, ty, st);
+}
+
+hipError_t launch_finalize(const FinArgs& a, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_inst), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_counter(long long* c, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, st, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_active(const Inst* insts, int n, int* out, hipStream_t st) {
+    hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(256), 0, st, insts, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, hipStream_t st) {
+    dim3 g((max_nodes + 255) / 256, n_inst), b(256);
+    if (prec == 0) hipLaunchKernelGGL((init_kernel<double, double, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((init_kernel<float, float, true>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_state(int prec, const StateArgs& a, int nodes, hipStream_t st) {
+    dim3 g((nodes + 255) / 256), b(256);
+    if (prec == 0) hipLaunchKernelGGL((state_kernel<double, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((state_kernel<float, true>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,77 @@
+"""The C-ABI library: it loads, exports every function include/lbm.h
+declares, and rejects invalid parameters before touching a device.  No
+compute calls here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2210_07501_amd import inputs, lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt))
+    # typedef'd function-pointer types are not exports
+    names -= {"lbm_alloc_fn", "lbm_free_fn"}
+    return names
+
+
+def test_library_exports_every_declared_function():
+    L = lbm.load()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    assert names == set(lbm.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_params_struct_layout():
+    # 4 int32 followed by 18 doubles, no padding
+    assert ctypes.sizeof(lbm.lbm_params) == 4 * 4 + 18 * 8
+    txt = open(HEADER).read()
+    body = txt[txt.index("typedef struct {"):txt.index("} lbm_params;")]
+    doubles = sum(len(re.findall(r"\b[A-Za-z_0-9]+\b", decl)) for decl in re.findall(r"double\s+([^;]+);", body))
+    assert doubles == 18
+
+
+def _create(cfg, n_inst=1, prec=0):
+    L = lbm.load()
+    arr = (lbm.lbm_params * n_inst)(*[lbm.make_params(cfg)] * n_inst)
+    h = ctypes.c_void_p()
+    rc = L.lbm_create(arr, n_inst, prec, None, lbm.ALLOC_FN(), lbm.FREE_FN(), None, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=2), dict(ny=3), dict(n_waves=3), dict(n_waves=0), dict(W=0.0), dict(b=3.0),
+    dict(b=62.0), dict(M_phi=0.0), dict(mu_a=-0.1), dict(k_b=0.0), dict(rho_a=0.0),
+    dict(sigma_T=float("nan")), dict(T_h=float("inf")),
+])
+def test_create_rejects_invalid_parameters(bad):
+    cfg = inputs.small_channel()
+    cfg.update(bad)
+    rc, h = _create(cfg)
+    assert rc == lbm.LBM_EINVAL
+    assert not h.value
+
+
+def test_create_rejects_bad_arguments():
+    rc, _ = _create(inputs.small_channel(), n_inst=0)
+    assert rc == lbm.LBM_EINVAL
+    rc, _ = _create(inputs.small_channel(), prec=7)
+    assert rc == lbm.LBM_EINVAL
+    L = lbm.load()
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_init(None, None) == lbm.LBM_EINVAL
+    assert L.lbm_set_tile(None, 32, 8) == lbm.LBM_EINVAL
+
+
+def test_strerror():
+    for s in (0, -1, -2, -3, -4, -5, -99):
+        assert isinstance(lbm.lbm_strerror(s), str)

@@ -1,0 +1,194 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on the
+same seeded inputs, float64 storage.  Bar: 1e-11 relative max-norm on the
+populations and on phi, T, p; u on the momentum-population scale."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2210_07501_amd import inputs
+from tests._parity import TOL64, compare_fields, compare_state, rel_maxnorm, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2210_07501_amd import lbm as L
+    L.load()
+    return L
+
+
+def gpu_run(L, cfg, steps, fields=None, prec=0, tile=None):
+    ctx = L.lbm_create(cfg, precision=prec)
+    if tile:
+        L.lbm_set_tile(ctx, *tile)
+    L.lbm_init(ctx, None if fields is None else [fields])
+    L.lbm_step(ctx, steps)
+    return ctx
+
+
+def test_small_channel_2000_steps(lbm):
+    """128 x 64 SRF channel from rest, 2000 steps, node by node."""
+    cfg = inputs.small_channel()
+    print("case: small channel 128x64, 2000 steps", flush=True)
+    ctx = gpu_run(lbm, cfg, 2000)
+    o = run_oracle(cfg, 2000)
+    pop = lbm.lbm_get_state(ctx)
+    errs = compare_state(pop, o.pop)
+    gf = lbm.lbm_fields(ctx)
+    of = o.fields()
+    ferrs = compare_fields(gf, of, np.max(np.abs(o.pop[1])))
+    print("population errors", errs, "field errors", ferrs, flush=True)
+    res = lbm.lbm_residual(ctx)
+    assert res["steps"] == 2000
+    assert not res["diverged"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_seeded_variants(lbm, seed):
+    """Displaced interface, temperature noise, random viscosity and
+    conductivity ratios: curvature and x-asymmetry the flat case lacks."""
+    cfg = inputs.perturbed_params(inputs.small_channel(), seed)
+    fields = inputs.perturbed_fields(cfg, seed)
+    print("case: seeded variant", seed, flush=True)
+    ctx = gpu_run(lbm, cfg, 600, fields=fields)
+    o = run_oracle(cfg, 600, fields=fields)
+    compare_state(lbm.lbm_get_state(ctx), o.pop)
+    compare_fields(lbm.lbm_fields(ctx), o.fields(), np.max(np.abs(o.pop[1])))
+
+
+@pytest.mark.parametrize("shape", [
+    dict(nx=100, ny=36, n_waves=2, b=17.0),   # ragged in x and y for every tile shape
+    dict(nx=4, ny=12, n_waves=1, b=6.0),      # narrower than any tile: periodic wrap inside a tile
+    dict(nx=36, ny=10, n_waves=3, b=5.0),     # thinnest layers the parameters allow
+    dict(nx=65, ny=33, n_waves=5, b=20.0),    # odd sizes
+])
+def test_ragged_and_tiny_lattices(lbm, shape):
+    cfg = inputs.cfg(sigma_T=-1e-4, sigma_TT=2e-4, mu_a=0.05, k_a=0.3, **shape)
+    fields = inputs.perturbed_fields(cfg, 7, amp=0.8)
+    print("case: ragged", shape, flush=True)
+    ctx = gpu_run(lbm, cfg, 300, fields=fields)
+    o = run_oracle(cfg, 300, fields=fields)
+    compare_state(lbm.lbm_get_state(ctx), o.pop)
+
+
+@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (16, 16), (64, 8)])
+def test_every_tile_shape(lbm, tile):
+    cfg = inputs.perturbed_params(inputs.small_channel(), 5)
+    fields = inputs.perturbed_fields(cfg, 5)
+    print("case: tile", tile, flush=True)
+    ctx = gpu_run(lbm, cfg, 200, fields=fields, tile=tile)
+    o = run_oracle(cfg, 200, fields=fields)
+    compare_state(lbm.lbm_get_state(ctx), o.pop)
+
+
+def test_init_from_fields_matches_oracle(lbm):
+    cfg = inputs.small_channel()
+    phi, ux, uy, T = inputs.perturbed_fields(cfg, 3)
+    rng = np.random.default_rng(3)
+    ux = 1e-3 * rng.standard_normal(phi.shape)
+    uy = 1e-3 * rng.standard_normal(phi.shape)
+    ctx = gpu_run(lbm, cfg, 0, fields=(phi, ux, uy, T))
+    o = run_oracle(cfg, 0, fields=(phi, ux, uy, T))
+    compare_state(lbm.lbm_get_state(ctx), o.pop, tol=1e-14)
+
+
+def test_state_roundtrip_is_exact(lbm):
+    cfg = inputs.cfg(nx=64, ny=32, b=16.0, sigma_TT=1e-4)
+    o = run_oracle(cfg, 50)
+    ctx = lbm.lbm_create(cfg)
+    lbm.lbm_init(ctx)
+    lbm.lbm_set_state(ctx, 0, o.pop)
+    back = lbm.lbm_get_state(ctx)
+    assert np.array_equal(back, o.pop)
+    # continuing from the set state matches continuing the oracle
+    lbm.lbm_step(ctx, 100)
+    o.step(100)
+    compare_state(lbm.lbm_get_state(ctx), o.pop)
+
+
+def test_zero_steps_is_identity(lbm):
+    cfg = inputs.small_channel()
+    ctx = gpu_run(lbm, cfg, 10)
+    a = lbm.lbm_get_state(ctx)
+    lbm.lbm_step(ctx, 0)
+    assert np.array_equal(lbm.lbm_get_state(ctx), a)
+
+
+def test_batched_channels_of_uneven_size(lbm):
+    """Three channels of different size and parameters in one context: each
+    must match its own oracle run."""
+    cfgs = [inputs.cfg(nx=128, ny=64, b=32.0, sigma_TT=1e-4),
+            inputs.cfg(nx=96, ny=40, n_waves=2, b=12.0, sigma_T=-2e-4, mu_a=0.3, k_a=0.05),
+            inputs.cfg(nx=256, ny=24, n_waves=4, b=14.0, sigma_T=1e-4, sigma_TT=3e-4, mu_a=0.02, k_a=0.5)]
+    fields = [inputs.perturbed_fields(c, 11 + k) for k, c in enumerate(cfgs)]
+    ctx = lbm.lbm_create(cfgs)
+    lbm.lbm_init(ctx, fields)
+    lbm.lbm_step(ctx, 250)
+    for k, c in enumerate(cfgs):
+        o = run_oracle(c, 250, fields=fields[k])
+        compare_state(lbm.lbm_get_state(ctx, k), o.pop)
+
+
+def test_check_records_match_oracle(lbm):
+    """The float64 reductions: sum phi, sum rho and the residual at the check
+    of step 200 (u and T at steps 100 and 200)."""
+    cfg = inputs.perturbed_params(inputs.small_channel(), 2)
+    fields = inputs.perturbed_fields(cfg, 2)
+    ctx = gpu_run(lbm, cfg, 250, fields=fields)
+    o = orc.Oracle(cfg)
+    o.init_fields(*fields)
+    o.step(100)
+    f100 = o.fields()
+    o.step(100)
+    f200 = o.fields()
+    res = lbm.lbm_residual(ctx)
+    assert res["steps"] == 250
+    rho = cfg["rho_a"] + f200["phi"] * (cfg["rho_b"] - cfg["rho_a"])
+    assert res["sum_phi"] == pytest.approx(np.sum(f200["phi"]), rel=1e-12)
+    assert res["sum_mass"] == pytest.approx(np.sum(rho), rel=1e-12)
+    r_ref = orc.residual(f100, f200, 100, cfg["T_ref"])
+    assert res["r"] == pytest.approx(r_ref, rel=1e-6)
+
+
+def test_phi_and_mass_conserved_on_gpu(lbm):
+    cfg = inputs.perturbed_params(inputs.small_channel(), 1)
+    fields = inputs.perturbed_fields(cfg, 1)
+    ctx = gpu_run(lbm, cfg, 101, fields=fields)
+    r0 = lbm.lbm_residual(ctx)
+    lbm.lbm_step(ctx, 2000)
+    r1 = lbm.lbm_residual(ctx)
+    assert r1["sum_phi"] == pytest.approx(r0["sum_phi"], rel=1e-12)
+    assert r1["sum_mass"] == pytest.approx(r0["sum_mass"], rel=1e-12)
+
+
+def test_solve_retires_converged_channel(lbm):
+    """lbm_solve: a channel at rest converges at its second check and stops
+    advancing; the other keeps stepping.  Both match the oracle at their own
+    step counts."""
+    still = inputs.cfg(nx=64, ny=32, b=16.0, dT=0.0)            # isothermal, no flow
+    live = inputs.cfg(nx=64, ny=32, b=16.0, sigma_TT=2e-4)
+    ctx = lbm.lbm_create([still, live])
+    lbm.lbm_init(ctx)
+    rc, active = lbm.lbm_solve(ctx, 1e-30, 600)
+    assert rc == 0 and active == 1
+    r_still = lbm.lbm_residual(ctx, 0)
+    r_live = lbm.lbm_residual(ctx, 1)
+    assert r_still["steps"] == 101
+    assert r_live["steps"] == 600
+    compare_state(lbm.lbm_get_state(ctx, 0), run_oracle(still, 101).pop)
+    compare_state(lbm.lbm_get_state(ctx, 1), run_oracle(live, 600).pop)
+
+
+def test_full_size_throughput_channel(lbm):
+    """4096 x 2048, 8 wavelengths, in the launch configuration of the
+    benchmark: 3 steps from rest against the oracle, every node."""
+    cfg = inputs.throughput_channel()
+    print("case: 4096x2048 float64, 3 steps", flush=True)
+    ctx = gpu_run(lbm, cfg, 3)
+    pop = lbm.lbm_get_state(ctx)
+    del ctx
+    o = run_oracle(cfg, 3)
+    compare_state(pop, o.pop)
