@@ -29,7 +29,8 @@
  *     printed (-u_x u_y^2, -u_x^2 u_y);
  *   - the interface delta function 1.5 W |grad phi|^2 multiplies both force
  *     components (the component form in Sec. 3 drops the 1.5 W);
- *   - n = 0 where |grad phi| <= 1e-12;
+ *   - n = grad phi / sqrt(|grad phi|^2 + 1e-12) (regularised where grad phi
+ *     vanishes, so that rounding noise in the bulk phases is not sharpened);
  *   - F_p = -grad(p* - rho c_s^2) uses p* = sum_a g_a of the current step;
  *   - curvature = isotropic divergence of n evaluated at the 8 neighbours;
  *   - stencil ghost rows: phi, p*, rho mirrored about the wall plane,
@@ -61,6 +62,8 @@ static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const double WGT[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                               1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 static const double CS2 = 1.0 / 3.0;
+/* regularisation of the unit normal where grad phi vanishes */
+static const double EPS_N = 1e-6;
 
 /* Moment order of the paper: (00,10,01,20,02,11,21,12,22). */
 static const int MM[9] = {0, 1, 0, 2, 0, 1, 2, 1, 2};
@@ -341,16 +344,11 @@ static void fill_macros(const orc_params* P, const double* pop, work_t* w) {
         for (int i = 0; i < nx; ++i) {
             double gx, gy;
             ISO_GRAD(ACC_PHI, j, i, gx, gy);
-            double mag = sqrt(gx * gx + gy * gy);
+            double den = sqrt(gx * gx + gy * gy + EPS_N * EPS_N);
             P1(w->gx, j, i) = gx;
             P1(w->gy, j, i) = gy;
-            if (mag > 1e-12) {
-                P1(w->nxf, j, i) = gx / mag;
-                P1(w->nyf, j, i) = gy / mag;
-            } else {
-                P1(w->nxf, j, i) = 0.0;
-                P1(w->nyf, j, i) = 0.0;
-            }
+            P1(w->nxf, j, i) = gx / den;
+            P1(w->nyf, j, i) = gy / den;
         }
 #undef ACC_PHI
 }

@@ -295,15 +295,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->user = user;
     c->params.assign(params, params + n_inst);
     c->retired.assign(n_inst, 0);
-    if (hip_stream) {
-        c->stream = (hipStream_t)hip_stream;
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete c;
-            return fail_hip(nullptr, hipErrorUnknown, "hipStreamCreate");
-        }
-        c->own_stream = true;
-    }
+    // NULL selects the null stream (ordered with all blocking streams)
+    c->stream = (hipStream_t)hip_stream;
     // layout
     c->h_inst.resize(n_inst);
     long long pop = 0, nodes = 0, rows = 0;

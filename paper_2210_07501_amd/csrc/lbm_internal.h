@@ -10,6 +10,10 @@ namespace lbm {
 // steps (counted from initialisation).
 constexpr int CHECK_EVERY = 100;
 
+// Regularisation of the interface normal where grad phi vanishes:
+// n = grad phi / sqrt(|grad phi|^2 + EPS_N^2).
+constexpr double EPS_N = 1e-6;
+
 // Per-channel descriptor in device memory.
 struct Inst {
     int nx, ny, tiles_x, tile0;   // tile0: first entry of this channel in the tile table

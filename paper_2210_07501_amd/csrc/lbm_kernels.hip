@@ -243,10 +243,9 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
     }
     __syncthreads();
     for (int k = tid; k < LY1; k += NT) {
-        // reference normal: sign of the reference y-gradient (0 where it vanishes)
-        R g0 = R(0.5) * (s_phi0[k + 2] - s_phi0[k]);
-        R eps = sizeof(R) == 8 ? R(1e-12) : R(1e-6);
-        s_n0y[k] = DEV ? (g0 > eps ? R(1) : (g0 < -eps ? R(-1) : R(0))) : R(0);
+        // reference normal of the x-invariant reference profile (regularised)
+        const R g0 = R(0.5) * (s_phi0[k + 2] - s_phi0[k]);
+        s_n0y[k] = DEV ? g0 / sqrt(g0 * g0 + R(EPS_N * EPS_N)) : R(0);
     }
 
     // ---- phase 1: pull own node (27 values kept) and the halo ring --------
@@ -322,7 +321,11 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
     __syncthreads();
 
     // ---- phase 2: interface normal on the tile + 1 ring ----------------------
-    const R eps_n = sizeof(R) == 8 ? R(1e-12) : R(1e-6);
+    // n = grad phi / sqrt(|grad phi|^2 + eps^2); stored as n_x and the
+    // deviation n_y - n0_y from the reference normal, formed without
+    // cancellation: with G = G0 + g (g the deviation part),
+    //   D0 - D = (-g_y (G_y + G0_y) - G_x^2) / (D0 + D),
+    //   n_y - n0_y = (G0_y (D0 - D) + g_y D0) / (D D0).
     for (int k = tid; k < LY1 * LX1; k += NT) {
         const int hy = k / LX1 - 1, hx = k % LX1 - 1;
         const int jj = y0 + hy;
@@ -332,22 +335,15 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
             const R E = c[1], Wv = c[-1], N = c[LX2], Sv = c[-LX2];
             const R NE = c[LX2 + 1], NW = c[LX2 - 1], SE = c[-LX2 + 1], SW = c[-LX2 - 1];
             const R Gx = (E - Wv) * (R(1) / R(3)) + (NE - NW + SE - SW) * (R(1) / R(12));
+            const R gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12));
             const R G0y = R(0.5) * (s_phi0[hy + 3] - s_phi0[hy + 1]);
-            const R Gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12)) + G0y;
-            const R mag = sqrt(Gx * Gx + Gy * Gy);
-            const R n0 = s_n0y[hy + 1];
-            if (mag > eps_n) {
-                nxv = Gx / mag;
-                if (n0 != R(0) && ((Gy > R(0)) == (n0 > R(0)))) {
-                    // n_y - n0 without cancellation: -Gx^2 / ((Gy + n0 |G|) |G|)
-                    dny = -(Gx * Gx) / ((Gy + n0 * mag) * mag);
-                } else {
-                    dny = Gy / mag - n0;
-                }
-            } else {
-                nxv = R(0);
-                dny = -n0;
-            }
+            const R Gy = gy + G0y;
+            const R eps2 = R(EPS_N * EPS_N);
+            const R D = sqrt(Gx * Gx + Gy * Gy + eps2);
+            const R D0 = sqrt(G0y * G0y + eps2);
+            const R dD = (-gy * (Gy + G0y) - Gx * Gx) / (D0 + D);
+            nxv = Gx / D;
+            dny = (G0y * dD + gy * D0) / (D * D0);
         }
         s_nx[k] = nxv;
         s_dny[k] = dny;

@@ -150,7 +150,9 @@ def lbm_create(cfgs, precision: int = LBM_FP64, stream=None, torch_alloc: bool =
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         alloc = _TorchAllocator(dev)
         if stream is None:
-            st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+            # torch's current stream (handle 0 is the null stream, which the
+            # library also takes for NULL)
+            st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream or None)
     h = ctypes.c_void_p()
     a_cb = alloc.alloc_cb if alloc else ALLOC_FN()
     f_cb = alloc.free_cb if alloc else FREE_FN()

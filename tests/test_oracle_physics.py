@@ -29,8 +29,11 @@ def test_flat_isothermal_interface_stays_at_rest():
     o.init_cold()
     o.step(2000)
     F = o.fields()
-    assert np.max(np.abs(F["ux"])) <= 1e-15
-    assert np.max(np.abs(F["uy"])) <= 1e-15
+    # u_x vanishes exactly (x-invariance); u_y stays at rounding level: the
+    # regularised normal leaves a static normal force of ~1e-14 in the far
+    # tails, balanced by pressure.
+    assert np.max(np.abs(F["ux"])) == 0.0
+    assert np.max(np.abs(F["uy"])) <= 1e-14
 
 
 def test_vertical_gradient_keeps_x_invariance_bitwise():
