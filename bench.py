@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=str, default="")
+    ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a single channel (or a batch of channels) "
@@ -110,8 +113,18 @@ def main():
     torch.cuda.set_device(0)
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     cfg = inputs.throughput_channel()
+    if args.calib_copy:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("bench: calibration copy of 1 GiB x 3 done")
+    precs = {"both": (lbm.LBM_FP64, lbm.LBM_FP32_DEV), "fp64": (lbm.LBM_FP64,),
+             "fp32": (lbm.LBM_FP32_DEV,)}[args.precision]
     out = {}
-    for prec in (lbm.LBM_FP64, lbm.LBM_FP32_DEV):
+    for prec in precs:
         log("bench: precision %d, %d warmup + %d timed steps on %dx%d" % (prec, args.warmup, args.steps,
                                                                         cfg["nx"], cfg["ny"]))
         out[prec] = run_gpu(cfg, prec, args.steps, args.warmup, tile)
@@ -127,6 +140,13 @@ def main():
                 "traffic": (traffic * r["nodes"]) if traffic else None,
                 "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_update": bpu}
 
+    if lbm.LBM_FP64 not in out or lbm.LBM_FP32_DEV not in out:
+        # partial runs (profiling) print the per-precision numbers only
+        for prec, r in out.items():
+            log("bench: precision %d: %.1f MLUPS, kernel %.4f ms" % (
+                prec, r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6, r["kernel_ms"]))
+        print(json.dumps({str(p): roof(p) for p in out}), flush=True)
+        return
     r64 = out[lbm.LBM_FP64]
     mlups64 = r64["nodes"] * args.steps / (r64["ms_total"] * 1e-3) / 1e6
     r32 = out[lbm.LBM_FP32_DEV]

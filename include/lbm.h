@@ -131,7 +131,8 @@ int lbm_set_state(lbm_ctx* ctx, int32_t inst, const double* pop);
 int lbm_profile_steps(lbm_ctx* ctx, int64_t n, double* ms);
 
 /* Tile shape of the fused step kernel: tx x ty nodes per workgroup from the
- * compiled set {32x8, 64x4, 16x16, 64x8}.  0,0 picks the default. */
+ * compiled set {64x8 (default), 32x8, 64x4, 16x16, 64x16, 128x8}; 0,0 picks
+ * the default.  LBM_EINVAL for any other shape. */
 int lbm_set_tile(lbm_ctx* ctx, int32_t tx, int32_t ty);
 
 /* Number of lattice nodes over all instances, and device bytes held. */

@@ -26,32 +26,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def flags() -> list:
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+def flags(extra=()) -> list:
+    return list(extra) + ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link the shared library (always rebuilds)."""
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every HIP source and link the shared library (always rebuilds).
+    defines: extra -D options (kernel variants for tuning builds)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build", os.path.basename(out).replace(".so", ""))
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + flags(defines) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

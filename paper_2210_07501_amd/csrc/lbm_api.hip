@@ -33,14 +33,15 @@ struct lbm_ctx {
     std::vector<lbm_params> params;
     std::vector<Inst> h_inst;
     std::vector<int> h_tile_inst;
-    long long total_nodes = 0, total_pop = 0, total_rows = 0;
+    long long total_nodes = 0, total_pop = 0, total_rows = 0, total_cols = 0;
     int max_nodes = 0;
     int n_tiles = 0;
-    int tx = 32, ty = 8;
+    int tx = TILE_SHAPES[0][0], ty = TILE_SHAPES[0][1];
     // device memory
     void* popA = nullptr;
     void* popB = nullptr;
     void* phi0 = nullptr;
+    void* twall = nullptr;             // bottom-wall temperature by column
     double* snap = nullptr;            // 4 * total_nodes
     double* partials = nullptr;        // n_tiles * 8 (capacity for the smallest tile)
     int partial_cap = 0;
@@ -136,14 +137,22 @@ int tiles_of(const lbm_params& p, int tx, int ty, int* tiles_x) {
     return txs * tys;
 }
 
+// Tile layout of a channel: tiles_x, tiles_y and the strip width (in tiles).
+// Eight strips across the channel: a channel that fills the GPU hands one
+// strip to each of the eight XCDs.
+void set_layout(Inst& I, const lbm_params& p, int tx, int ty) {
+    I.tiles_x = (p.nx + tx - 1) / tx;
+    I.tiles_y = (p.ny + ty - 1) / ty;
+    I.strip_w = std::max(1, (I.tiles_x + 7) / 8);
+}
+
 // Build the tile table for the current tile shape over the channels whose
 // host flag says active (all channels when all == true).
 int build_tiles(lbm_ctx* c, bool all) {
     c->h_tile_inst.clear();
     for (int k = 0; k < c->n_inst; ++k) {
-        int txs = 0;
-        int nt = tiles_of(c->params[k], c->tx, c->ty, &txs);
-        c->h_inst[k].tiles_x = txs;
+        int nt = tiles_of(c->params[k], c->tx, c->ty, nullptr);
+        set_layout(c->h_inst[k], c->params[k], c->tx, c->ty);
         c->h_inst[k].ntiles = nt;
         c->h_inst[k].tile0 = (int)c->h_tile_inst.size();
         if (all || !c->retired[k]) {
@@ -181,6 +190,7 @@ void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
     a.src_v = parity ? c->popB : c->popA;
     a.dst_v = parity ? c->popA : c->popB;
     a.phi0_v = c->phi0;
+    a.tw_v = c->twall;
     for (int k = 0; k < 4; ++k) a.snap[k] = c->snap + (size_t)k * c->total_nodes;
     a.partials = c->partials;
     for (int k = 0; k < 5; ++k) a.out[k] = nullptr;
@@ -299,7 +309,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->stream = (hipStream_t)hip_stream;
     // layout
     c->h_inst.resize(n_inst);
-    long long pop = 0, nodes = 0, rows = 0;
+    long long pop = 0, nodes = 0, rows = 0, cols = 0;
     int min_tile_nodes = 16 * 16;  // smallest compiled tile: capacity for tile tables
     long long max_tiles = 0;
     for (int k = 0; k < n_inst; ++k) {
@@ -312,6 +322,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         I.pop_off = pop;
         I.node_off = nodes;
         I.row_off = rows;
+        I.col_off = cols;
         I.W = p.W;
         I.M_phi = p.M_phi;
         I.w_phi = 1.0 / (3.0 * p.M_phi + 0.5);
@@ -328,23 +339,25 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         pop += 27 * n;
         nodes += n;
         rows += p.ny + 4;
+        cols += p.nx;
         c->max_nodes = std::max<long long>(c->max_nodes, n);
         // worst case over the compiled tile shapes (16 x 16 and 32 x 8 and 64 x 4 and 64 x 8)
         long long t = 0;
-        const int shapes[4][2] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}};
-        for (auto& s : shapes) t = std::max<long long>(t, (long long)tiles_of(p, s[0], s[1], nullptr));
+        for (auto& s : TILE_SHAPES) t = std::max<long long>(t, (long long)tiles_of(p, s[0], s[1], nullptr));
         max_tiles += t;
     }
     (void)min_tile_nodes;
     c->total_pop = pop;
     c->total_nodes = nodes;
     c->total_rows = rows;
+    c->total_cols = cols;
     c->tile_cap = (int)max_tiles;
     c->partial_cap = (int)max_tiles;
     int rc = LBM_OK;
     c->popA = dev_alloc(c, (size_t)pop * c->elem);
     c->popB = dev_alloc(c, (size_t)pop * c->elem);
     c->phi0 = dev_alloc(c, (size_t)rows * c->elem);
+    c->twall = dev_alloc(c, (size_t)cols * c->elem);
     c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
     c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
     c->d_inst = (Inst*)dev_alloc(c, sizeof(Inst) * n_inst);
@@ -353,7 +366,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->d_counter = (long long*)dev_alloc(c, sizeof(long long));
     c->d_tol = (double*)dev_alloc(c, sizeof(double));
     c->d_active = (int*)dev_alloc(c, sizeof(int));
-    if (!c->popA || !c->popB || !c->phi0 || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
+    if (!c->popA || !c->popB || !c->phi0 || !c->twall || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
         !c->d_res || !c->d_counter || !c->d_tol || !c->d_active) {
         rc = LBM_ENOMEM;
     }
@@ -376,6 +389,24 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
             if (hipMemcpy(c->phi0, rf.data(), rows * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
                 rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
         }
+    }
+    if (rc == LBM_OK) {
+        // bottom-wall temperature T_h + dT cos(2 pi i / l) for every column
+        std::vector<double> td(cols);
+        for (int k = 0; k < n_inst; ++k) {
+            const lbm_params& p = params[k];
+            const double l = (double)p.nx / (double)p.n_waves;
+            for (int i = 0; i < p.nx; ++i)
+                td[c->h_inst[k].col_off + i] = p.T_h + p.dT * std::cos(2.0 * M_PI * (double)i / l);
+        }
+        hipError_t e;
+        if (precision == LBM_FP64) {
+            e = hipMemcpy(c->twall, td.data(), cols * sizeof(double), hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> tf(td.begin(), td.end());
+            e = hipMemcpy(c->twall, tf.data(), cols * sizeof(float), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) rc = fail_hip(c, e, "upload wall temperatures");
     }
     if (rc == LBM_OK) rc = build_tiles(c, true);
     if (rc == LBM_OK) {
@@ -410,8 +441,9 @@ void lbm_destroy(lbm_ctx* c) {
 
 int lbm_set_tile(lbm_ctx* c, int32_t tx, int32_t ty) {
     if (!c) return LBM_EINVAL;
-    if (tx == 0 && ty == 0) { tx = 32; ty = 8; }
-    const bool ok = (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 16) || (tx == 64 && ty == 8);
+    if (tx == 0 && ty == 0) { tx = TILE_SHAPES[0][0]; ty = TILE_SHAPES[0][1]; }
+    bool ok = false;
+    for (auto& s : TILE_SHAPES) ok = ok || (s[0] == tx && s[1] == ty);
     if (!ok) return LBM_EINVAL;
     if (c->initialised && (c->steps % 2) != 0) {
         // the tile shape may change at any step; buffers are unaffected
@@ -554,7 +586,7 @@ int lbm_fields(lbm_ctx* c, int32_t inst, double* phi, double* ux, double* uy, do
     int nt = tiles_of(P, c->tx, c->ty, &txs);
     Inst I = c->h_inst[inst];
     I.tile0 = 0;
-    I.tiles_x = txs;
+    set_layout(I, P, c->tx, c->ty);
     I.ntiles = nt;
     I.node_off = 0;
     I.active = 1;

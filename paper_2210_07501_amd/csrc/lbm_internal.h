@@ -10,6 +10,11 @@ namespace lbm {
 // steps (counted from initialisation).
 constexpr int CHECK_EVERY = 100;
 
+// Tile shapes (nodes per workgroup, x by y) compiled for the fused step
+// kernel; the first one is the default.
+constexpr int N_TILE_SHAPES = 6;
+constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{64, 8}, {32, 8}, {64, 4}, {16, 16}, {64, 16}, {128, 8}};
+
 // Regularisation of the interface normal where grad phi vanishes:
 // n = grad phi / sqrt(|grad phi|^2 + EPS_N^2).
 constexpr double EPS_N = 1e-6;
@@ -17,10 +22,11 @@ constexpr double EPS_N = 1e-6;
 // Per-channel descriptor in device memory.
 struct Inst {
     int nx, ny, tiles_x, tile0;   // tile0: first entry of this channel in the tile table
-    int ntiles, active, pad0, pad1;
+    int ntiles, active, tiles_y, strip_w;  // tiles are ordered in column strips of strip_w tiles
     long long pop_off;            // element offset of the channel in the population buffers
     long long node_off;           // element offset in node-sized arrays
     long long row_off;            // offset in the reference-row table (ny + 4 rows)
+    long long col_off;            // offset in the bottom-wall temperature table (nx columns)
     double W, M_phi, w_phi, b;
     double rho_a, rho_b, mu_a, mu_b, k_a, k_b;
     double s0, sT, sTT, T_ref;
@@ -42,6 +48,7 @@ struct StepArgs {
     const void* src_v;
     void* dst_v;
     const void* phi0_v;           // reference rows (compute type)
+    const void* tw_v;             // bottom-wall temperature by column (compute type)
     double* snap[4];              // ux, uy, T, phi at the last check
     double* partials;             // [tile][8]
     double* out[5];               // fields: phi, ux, uy, T, p

@@ -37,9 +37,17 @@ __device__ __forceinline__ int modx(int i, int nx) {
     return r < 0 ? r + nx : r;
 }
 
-// D2Q9: index -> (e_x, e_y); weights; opposite; e_y-mirror.
-__device__ __constant__ int c_ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ __constant__ int c_ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+// D2Q9: index -> (e_x, e_y), e_x = (0,1,0,-1,0,1,-1,-1,1), e_y = (0,0,1,0,-1,1,1,-1,-1);
+// opposite direction; direction with e_y reversed.  Compile-time functions so
+// that unrolled loops fold them to constants.
+__host__ __device__ constexpr int EX(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0); }
+__host__ __device__ constexpr int EY(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0); }
+__host__ __device__ constexpr int OPP(int a) { return a == 0 ? 0 : (a <= 4 ? (a <= 2 ? a + 2 : a - 2) : (a <= 6 ? a + 2 : a - 2)); }
+__host__ __device__ constexpr int MIRY(int a) { return a == 2 ? 4 : a == 4 ? 2 : a == 5 ? 8 : a == 8 ? 5 : a == 6 ? 7 : a == 7 ? 6 : a; }
+// (1-D velocity index 0: 0, 1: +1, 2: -1) pair -> D2Q9 index
+__host__ __device__ constexpr int DIR(int cx, int cy) {
+    return cx == 0 ? (cy == 0 ? 0 : cy == 1 ? 2 : 4) : cx == 1 ? (cy == 0 ? 1 : cy == 1 ? 5 : 8) : (cy == 0 ? 3 : cy == 1 ? 6 : 7);
+}
 
 template <class R> struct W9 {
     static __device__ __forceinline__ R w(int a) {
@@ -50,12 +58,12 @@ template <class R> struct W9 {
 // Parameters of one channel converted to the compute type.
 template <class R> struct P {
     int nx, ny;
-    R W, M, w_phi, drho, rho_a, mu_a, dmu, k_a, dk;
+    R W, inv_W, M, w_phi, drho, rho_a, mu_a, dmu, k_a, dk;
     R s0, sT, sTT, dTref;  // dTref = T_r - T_ref
     R T_h, dT, T_c, kx, Fx, Fy, p_r, T_r;
     __device__ void load(const Inst& I) {
         nx = I.nx; ny = I.ny;
-        W = R(I.W); M = R(I.M_phi); w_phi = R(I.w_phi);
+        W = R(I.W); inv_W = R(1.0 / I.W); M = R(I.M_phi); w_phi = R(I.w_phi);
         rho_a = R(I.rho_a); drho = R(I.rho_b - I.rho_a);
         mu_a = R(I.mu_a); dmu = R(I.mu_b - I.mu_a);
         k_a = R(I.k_a); dk = R(I.k_b - I.k_a);
@@ -65,22 +73,27 @@ template <class R> struct P {
     }
 };
 
-template <class R> __device__ __forceinline__ R T_wall_bottom(const Inst& I, int i) {
-    // T_h + dT cos(2 pi i / l), evaluated in float64
-    return R(I.T_h + I.dT * cos(I.kx * (double)i));
+// Reciprocal and square root: correctly rounded in float64; in float32 the
+// hardware instructions (about 1 ulp), well inside the float32 tolerance.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Element index of population (d, a) at node (i, j) in a [3][9][ny][nx] block.
+__device__ __forceinline__ size_t pidx(int nx, int ny, int d, int a, int j, int i) {
+    return (((size_t)(d * 9 + a) * (size_t)ny + (size_t)j) * (size_t)nx + (size_t)i);
 }
 
 // ---------------------------------------------------------------------------
 // Factored moment maps on the D2Q9 tensor lattice.  Index m[3 * mx + my].
-// Direction of 1-D velocities (0, +1, -1) -> D2Q9 index.
-__device__ __constant__ int c_dir[3][3] = {{0, 2, 4}, {1, 5, 8}, {3, 6, 7}};
 
 // raw moments r[mx][my] = sum_a f_a e_x^mx e_y^my
 template <class R> __device__ __forceinline__ void raw_moments(const R* f, R* r) {
     R s[3][3];  // s[cx][my]
 #pragma unroll
     for (int cx = 0; cx < 3; ++cx) {
-        R f0 = f[c_dir[cx][0]], fp = f[c_dir[cx][1]], fm = f[c_dir[cx][2]];
+        R f0 = f[DIR(cx, 0)], fp = f[DIR(cx, 1)], fm = f[DIR(cx, 2)];
         s[cx][0] = f0 + fp + fm;
         s[cx][1] = fp - fm;
         s[cx][2] = fp + fm;
@@ -121,19 +134,38 @@ template <class R> __device__ __forceinline__ void raw_to_dist(const R* r, R* f)
     }
 #pragma unroll
     for (int cx = 0; cx < 3; ++cx) {
-        f[c_dir[cx][0]] = s[cx][0] - s[cx][2];
-        f[c_dir[cx][1]] = R(0.5) * (s[cx][1] + s[cx][2]);
-        f[c_dir[cx][2]] = R(0.5) * (s[cx][2] - s[cx][1]);
+        f[DIR(cx, 0)] = s[cx][0] - s[cx][2];
+        f[DIR(cx, 1)] = R(0.5) * (s[cx][1] + s[cx][2]);
+        f[DIR(cx, 2)] = R(0.5) * (s[cx][2] - s[cx][1]);
     }
 }
 
+// Post-collision populations are read again only by the next step, long
+// after this tile: stream them past the caches (non-temporal stores) so that
+// the halo rows still needed by neighbouring tiles stay in L2.
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 1
+#endif
+template <class S> __device__ __forceinline__ void store_pop(S* p, S v) {
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // ---------------------------------------------------------------------------
-// Populations: buffer layout [3][9][ny][nx] per channel.
+// Populations: buffer layout [3][9][ny][nx] per channel: 27 planes of
+// N = nx * ny values.  Plane pointers are uniform across a workgroup; the
+// node offset j * nx + i is a 32-bit index.
 template <class S> struct Pop {
     S* base;
-    int nx, ny;
-    __device__ __forceinline__ size_t idx(int d, int a, int j, int i) const {
-        return (((size_t)(d * 9 + a) * (size_t)ny + (size_t)j) * (size_t)nx + (size_t)i);
+    uint32_t N;
+    __device__ __forceinline__ S* plane(int d, int a) const { return base + (size_t)(d * 9 + a) * N; }
+    // value at node offset `off` of plane (d, a): a 32-bit byte offset from a
+    // uniform plane base (planes are far below 4 GiB)
+    __device__ __forceinline__ S ld(int d, int a, uint32_t off) const {
+        return *(const S*)((const char*)plane(d, a) + (off * (uint32_t)sizeof(S)));
     }
 };
 
@@ -141,33 +173,34 @@ template <class S> struct Pop {
 // post-collision buffer, with the wall schemes of Sec. 5: g half-way
 // bounce-back, h anti-bounce-back to the wall temperature, f specular
 // (free-slip).  Returned as deviations relative to row j's references.
-// NEED: bit 0 f, bit 1 g, bit 2 h.
+// NEED: bit 0 f, bit 1 g, bit 2 h.  tw: bottom-wall temperature by column.
 template <class S, class R, int NEED>
-__device__ __forceinline__ void pull_node(const Pop<S>& src, const Inst& I, const P<R>& p, int i,
+__device__ __forceinline__ void pull_node(const Pop<S>& src, const R* __restrict__ tw, const P<R>& p, int i,
                                           int j, R* f, R* g, R* h) {
     const int nx = p.nx, ny = p.ny;
-    const int im = wrapx(i - 1, nx), ip = wrapx(i + 1, nx);
-    // rows j (e_y = 0), j - 1 (e_y = +1), j + 1 (e_y = -1)
-    const bool has_s = j > 0, has_n = j < ny - 1;
+    const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+    const bool wall_s = j == 0, wall_n = j == ny - 1;
+    const uint32_t r0 = (uint32_t)j * (uint32_t)nx;
+    const uint32_t rs = wall_s ? r0 : r0 - (uint32_t)nx;   // clamped at the walls
+    const uint32_t rn = wall_n ? r0 : r0 + (uint32_t)nx;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const int ex = c_ex[a], ey = c_ey[a];
+        const int ex = EX(a), ey = EY(a);
         const int is = ex == 0 ? i : (ex > 0 ? im : ip);
-        const bool interior = ey == 0 || (ey > 0 ? has_s : has_n);
-        if (interior) {
-            const int js = j - ey;
-            if (NEED & 1) f[a] = R(src.base[src.idx(0, a, js, is)]);
-            if (NEED & 2) g[a] = R(src.base[src.idx(1, a, js, is)]);
-            if (NEED & 4) h[a] = R(src.base[src.idx(2, a, js, is)]);
-        } else {
-            // mirror_y(a) and opposite(a) for the 6 directions with e_y != 0
-            const int mir = (a == 2) ? 4 : (a == 4) ? 2 : (a == 5) ? 8 : (a == 8) ? 5 : (a == 6) ? 7 : 6;
-            const int opp = (a == 2) ? 4 : (a == 4) ? 2 : (a == 5) ? 7 : (a == 7) ? 5 : (a == 6) ? 8 : 6;
-            if (NEED & 1) f[a] = R(src.base[src.idx(0, mir, j, is)]);
-            if (NEED & 2) g[a] = R(src.base[src.idx(1, opp, j, i)]);
-            if (NEED & 4) {
-                const R Tw = (ey > 0) ? T_wall_bottom<R>(I, i) : p.T_c;
-                h[a] = -R(src.base[src.idx(2, opp, j, i)]) + R(2) * W9<R>::w(a) * (Tw - p.T_r);
+        const uint32_t off = (ey == 0 ? r0 : (ey > 0 ? rs : rn)) + (uint32_t)is;
+        if (NEED & 1) f[a] = R(src.ld(0, a, off));
+        if (NEED & 2) g[a] = R(src.ld(1, a, off));
+        if (NEED & 4) h[a] = R(src.ld(2, a, off));
+        if (ey != 0) {
+            const bool wall = ey > 0 ? wall_s : wall_n;
+            if (wall) {
+                const uint32_t o0 = r0 + (uint32_t)is, oi = r0 + (uint32_t)i;
+                if (NEED & 1) f[a] = R(src.ld(0, MIRY(a), o0));
+                if (NEED & 2) g[a] = R(src.ld(1, OPP(a), oi));
+                if (NEED & 4) {
+                    const R Tw = (ey > 0) ? tw[i] : p.T_c;
+                    h[a] = -R(src.ld(2, OPP(a), oi)) + R(2) * W9<R>::w(a) * (Tw - p.T_r);
+                }
             }
         }
     }
@@ -203,8 +236,15 @@ __device__ __forceinline__ void block_sum(double* v, double* red /* LDS [NT/64][
 // ---------------------------------------------------------------------------
 // Fused step kernel.
 // MODE 0: step; 1: step + residual snapshot; 2: fields only (no step).
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 0
+#endif
 template <int TX, int TY, class S, class R, bool DEV, int MODE>
-__global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(TX * TY)
+#if LBM_WAVES_PER_EU > 0
+__attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+#endif
+void step_kernel(StepArgs a) {
     constexpr int NT = TX * TY;
     constexpr int LX2 = TX + 4, LY2 = TY + 4;   // phi region (halo 2)
     constexpr int LX1 = TX + 2, LY1 = TY + 2;   // T, p*, n region (halo 1)
@@ -229,11 +269,28 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
     P<R> p;
     p.load(I);
     const int nx = p.nx, ny = p.ny;
-    const int lt = tile - I.tile0;
-    const int x0 = (lt % I.tiles_x) * TX, y0 = (lt / I.tiles_x) * TY;
+    // tile order within a channel: column strips of strip_w tiles, each
+    // strip row-major, so that a run of consecutive tiles (one XCD's share)
+    // covers a strip whose halo rows are still in that XCD's L2
+    int tcol, trow;
+    {
+        const int lt = tile - I.tile0;
+        const int SW = I.strip_w, full = I.tiles_x / SW, per = SW * I.tiles_y;
+        if (lt < full * per) {
+            const int s = lt / per, q = lt - s * per;
+            trow = q / SW;
+            tcol = s * SW + (q - trow * SW);
+        } else {
+            const int rw = I.tiles_x - full * SW, q = lt - full * per;
+            trow = q / rw;
+            tcol = full * SW + (q - trow * rw);
+        }
+    }
+    const int x0 = tcol * TX, y0 = trow * TY;
 
     const R* phi0t = (const R*)a.phi0_v;
-    Pop<S> src{(S*)a.src_v + I.pop_off, nx, ny};
+    Pop<S> src{(S*)a.src_v + I.pop_off, (uint32_t)nx * (uint32_t)ny};
+    const R* __restrict__ tw = (const R*)a.tw_v + I.col_off;
     const int tid = threadIdx.x;
 
     // reference rows
@@ -250,13 +307,13 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
 
     // ---- phase 1: pull own node (27 values kept) and the halo ring --------
     const int tx = tid % TX, ty = tid / TX;
-    const int gi = modx(x0 + tx, nx), gj = y0 + ty;
+    const int gi = (x0 + tx < nx) ? x0 + tx : modx(x0 + tx, nx), gj = y0 + ty;
     const bool own_row = gj < ny;
     const bool own_ok = own_row && (x0 + tx < nx);
     R f[9], g[9], h[9];
     R rf[9], rg[9], rh[9];
     if (own_row) {
-        pull_node<S, R, 7>(src, I, p, gi, gj, f, g, h);
+        pull_node<S, R, 7>(src, tw, p, gi, gj, f, g, h);
         raw_moments(f, rf);
         raw_moments(g, rg);
         raw_moments(h, rh);
@@ -271,11 +328,13 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
         else { int q = k - 4 * LX2; hy = q / 4; int c = q % 4; hx = c < 2 ? c - 2 : TX + c - 2; }
         const int jj = y0 + hy;
         if (jj < 0 || jj >= ny) continue;
-        const int ii = modx(x0 + hx, nx);
+        int ii = x0 + hx;
+        ii = ii < 0 ? ii + nx : ii;
+        ii = ii >= nx ? ((ii - nx < nx) ? ii - nx : modx(ii, nx)) : ii;
         const bool h1 = hx >= -1 && hx <= TX && hy >= -1 && hy <= TY;
         R tf[9], tg[9], th[9];
         if (h1) {
-            pull_node<S, R, 7>(src, I, p, ii, jj, tf, tg, th);
+            pull_node<S, R, 7>(src, tw, p, ii, jj, tf, tg, th);
             R s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) { s1 += tf[q]; s2 += tg[q]; s3 += th[q]; }
@@ -283,7 +342,7 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
             s_pb[(hy + 1) * LX1 + hx + 1] = s2;
             s_Tb[(hy + 1) * LX1 + hx + 1] = s3;
         } else {
-            pull_node<S, R, 1>(src, I, p, ii, jj, tf, tg, th);
+            pull_node<S, R, 1>(src, tw, p, ii, jj, tf, tg, th);
             R s1 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) s1 += tf[q];
@@ -311,7 +370,7 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
                 vp = s_pb[(mhy + 1) * LX1 + hx + 1];
                 const R Tm = s_Tb[(mhy + 1) * LX1 + hx + 1];
                 const int ii = modx(x0 + hx, nx);
-                const R Tw = (jj < 0) ? T_wall_bottom<R>(I, ii) : p.T_c;
+                const R Tw = (jj < 0) ? tw[ii] : p.T_c;
                 vT = R(2) * (Tw - p.T_r) - Tm;
             }
             s_pb[(hy + 1) * LX1 + hx + 1] = vp;
@@ -339,11 +398,19 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
             const R G0y = R(0.5) * (s_phi0[hy + 3] - s_phi0[hy + 1]);
             const R Gy = gy + G0y;
             const R eps2 = R(EPS_N * EPS_N);
-            const R D = sqrt(Gx * Gx + Gy * Gy + eps2);
-            const R D0 = sqrt(G0y * G0y + eps2);
-            const R dD = (-gy * (Gy + G0y) - Gx * Gx) / (D0 + D);
-            nxv = Gx / D;
-            dny = (G0y * dD + gy * D0) / (D * D0);
+            const R D2 = Gx * Gx + Gy * Gy + eps2, D02 = G0y * G0y + eps2;
+            if (sizeof(R) == 8) {
+                const R D = sqrt(D2), D0 = sqrt(D02);
+                const R dD = (-gy * (Gy + G0y) - Gx * Gx) / (D0 + D);
+                nxv = Gx / D;
+                dny = (G0y * dD + gy * D0) / (D * D0);
+            } else {
+                const R rD = rsqrt_(D2), rD0 = rsqrt_(D02);
+                const R D = D2 * rD, D0 = D02 * rD0;
+                const R dD = (-gy * (Gy + G0y) - Gx * Gx) * rcp(D0 + D);
+                nxv = Gx * rD;
+                dny = (G0y * dD + gy * D0) * (rD * rD0);
+            }
         }
         s_nx[k] = nxv;
         s_dny[k] = dny;
@@ -399,8 +466,9 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
         const R phb = rf[0];
         const R phi = s_phi0[ty + 2] + phb;
         const R rho = p.rho_a + phi * p.drho;
-        const R ux = (rg[3] + R(0.5) * cs2 * Ftx) / (rho * cs2);
-        const R uy = (rg[1] + R(0.5) * cs2 * Fty) / (rho * cs2);
+        const R rrho = rcp(rho);
+        const R ux = (rg[3] + R(0.5) * cs2 * Ftx) * (R(3) * rrho);
+        const R uy = (rg[1] + R(0.5) * cs2 * Fty) * (R(3) * rrho);
         const R Gam = Fpx * ux + Fpy * uy;
         const R pb = rg[0] + R(0.5) * Gam;          // p - p_r
         const R Tb = rh[0];                          // T - T_r
@@ -437,14 +505,14 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
             }
             // local relaxation rates
             const R mu = p.mu_a + phi * p.dmu, kc = p.k_a + phi * p.dk;
-            const R w_nu = R(1) / (R(3) * (mu / rho) + R(0.5));
-            const R w_T = R(1) / (R(3) * (kc / rho) + R(0.5));
+            const R w_nu = rcp(R(3) * (mu * rrho) + R(0.5));
+            const R w_T = rcp(R(3) * (kc * rrho) + R(0.5));
             const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
 
             // --- ACE (Sec. 4.1): relax first central moments to M theta n ---
             {
                 const R ph0 = s_phi0[ty + 2];
-                const R theta = R(4) * phi * (R(1) - phi) / p.W;
+                const R theta = R(4) * phi * (R(1) - phi) * p.inv_W;
                 const R k10 = rf[3] - ux * phi, k01 = rf[1] - uy * phi;
                 const R t10 = k10 + p.w_phi * (p.M * theta * nxv - k10);
                 const R t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
@@ -514,13 +582,14 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
                 raw_to_dist(c, g);
             }
             if (own_ok) {
-                Pop<S> dst{(S*)a.dst_v + I.pop_off, nx, ny};
+                Pop<S> dst{(S*)a.dst_v + I.pop_off, (uint32_t)nx * (uint32_t)ny};
+                const uint32_t off = (uint32_t)gj * (uint32_t)nx + (uint32_t)gi;
                 if (DEV) {
                     // f deviations relative to the row of the node that pulls them
                     const R ph0 = s_phi0[ty + 2];
 #pragma unroll
                     for (int q = 1; q < 9; ++q) {
-                        const int ey = c_ey[q];
+                        const int ey = EY(q);
                         if (ey == 0) continue;
                         const int jr = gj + ey;
                         const R phr = (jr >= 0 && jr < ny) ? s_phi0[ty + 2 + ey] : ph0;
@@ -529,9 +598,10 @@ __global__ __launch_bounds__(TX * TY) void step_kernel(StepArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    dst.base[dst.idx(0, q, gj, gi)] = S(f[q]);
-                    dst.base[dst.idx(1, q, gj, gi)] = S(g[q]);
-                    dst.base[dst.idx(2, q, gj, gi)] = S(h[q]);
+                    const uint32_t bo = off * (uint32_t)sizeof(S);
+                    store_pop((S*)((char*)dst.plane(0, q) + bo), S(f[q]));
+                    store_pop((S*)((char*)dst.plane(1, q) + bo), S(g[q]));
+                    store_pop((S*)((char*)dst.plane(2, q) + bo), S(h[q]));
                 }
             }
         }
@@ -696,24 +766,23 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     central_to_raw(cf, ux, uy); raw_to_dist(cf, ef);
     central_to_raw(cg, ux, uy); raw_to_dist(cg, eg);
     central_to_raw(ch, ux, uy); raw_to_dist(ch, eh);
-    Pop<S> dst{(S*)a.dst_v + I.pop_off, nx, ny};
+    S* dst = (S*)a.dst_v + I.pop_off;
     // inverse gather: the value that node (i, j) will pull for direction k
     for (int k = 0; k < 9; ++k) {
-        const int ex = c_ex[k], ey = c_ey[k];
+        const int ex = EX(k), ey = EY(k);
         const int js = j - ey;
         const int is = wrapx(i - ex, nx);
         const double w = W9<double>::w(k);
         if (js >= 0 && js < ny) {
-            dst.base[dst.idx(0, k, js, is)] = S(ef[k]);
-            dst.base[dst.idx(1, k, js, is)] = S(eg[k]);
-            dst.base[dst.idx(2, k, js, is)] = S(eh[k]);
+            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k]);
+            dst[pidx(nx, ny, 1, k, js, is)] = S(eg[k]);
+            dst[pidx(nx, ny, 2, k, js, is)] = S(eh[k]);
         } else {
-            const int mir = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 8 : (k == 8) ? 5 : (k == 6) ? 7 : 6;
-            const int opp = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 7 : (k == 7) ? 5 : (k == 6) ? 8 : 6;
+            const int mir = MIRY(k), opp = OPP(k);
             const double Tw = (ey > 0) ? I.T_h + I.dT * cos(I.kx * (double)i) : I.T_c;
-            dst.base[dst.idx(0, mir, j, is)] = S(ef[k]);
-            dst.base[dst.idx(1, opp, j, i)] = S(eg[k]);
-            dst.base[dst.idx(2, opp, j, i)] = S(2.0 * w * (Tw - Tr) - eh[k]);
+            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k]);
+            dst[pidx(nx, ny, 1, opp, j, i)] = S(eg[k]);
+            dst[pidx(nx, ny, 2, opp, j, i)] = S(2.0 * w * (Tw - Tr) - eh[k]);
         }
     }
 }
@@ -730,21 +799,20 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
     const int i = (int)(q % nx), j = (int)(q / nx);
     const double ph0 = DEV ? (double)((const float*)a.phi0_v)[I.row_off + j + 2] : 0.0;
     const double pr = DEV ? I.p_r : 0.0, Tr = DEV ? I.T_r : 0.0;
-    Pop<S> buf{(S*)a.buf_v + I.pop_off, nx, ny};
+    S* buf = (S*)a.buf_v + I.pop_off;
     for (int k = 0; k < 9; ++k) {
-        const int ex = c_ex[k], ey = c_ey[k];
+        const int ex = EX(k), ey = EY(k);
         const int js = j - ey;
         const int is = wrapx(i - ex, nx);
         const double w = W9<double>::w(k);
         size_t kf, kg, kh;
         double sgn_h = 1.0, add_h = 0.0;
         if (js >= 0 && js < ny) {
-            kf = buf.idx(0, k, js, is); kg = buf.idx(1, k, js, is); kh = buf.idx(2, k, js, is);
+            kf = pidx(nx, ny, 0, k, js, is); kg = pidx(nx, ny, 1, k, js, is); kh = pidx(nx, ny, 2, k, js, is);
         } else {
-            const int mir = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 8 : (k == 8) ? 5 : (k == 6) ? 7 : 6;
-            const int opp = (k == 2) ? 4 : (k == 4) ? 2 : (k == 5) ? 7 : (k == 7) ? 5 : (k == 6) ? 8 : 6;
+            const int mir = MIRY(k), opp = OPP(k);
             const double Tw = (ey > 0) ? I.T_h + I.dT * cos(I.kx * (double)i) : I.T_c;
-            kf = buf.idx(0, mir, j, is); kg = buf.idx(1, opp, j, i); kh = buf.idx(2, opp, j, i);
+            kf = pidx(nx, ny, 0, mir, j, is); kg = pidx(nx, ny, 1, opp, j, i); kh = pidx(nx, ny, 2, opp, j, i);
             sgn_h = -1.0;
             add_h = 2.0 * w * (Tw - Tr);
         }
@@ -752,14 +820,14 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
         const size_t o1 = ((size_t)(1 * 9 + k) * ny + j) * nx + i;
         const size_t o2 = ((size_t)(2 * 9 + k) * ny + j) * nx + i;
         if (a.dir == 0) {
-            a.state[o0] = w * ph0 + (double)buf.base[kf];
-            a.state[o1] = w * pr + (double)buf.base[kg];
-            a.state[o2] = w * Tr + sgn_h * (double)buf.base[kh] + add_h;
+            a.state[o0] = w * ph0 + (double)buf[kf];
+            a.state[o1] = w * pr + (double)buf[kg];
+            a.state[o2] = w * Tr + sgn_h * (double)buf[kh] + add_h;
         } else {
-            buf.base[kf] = S(a.state[o0] - w * ph0);
-            buf.base[kg] = S(a.state[o1] - w * pr);
+            buf[kf] = S(a.state[o0] - w * ph0);
+            buf[kg] = S(a.state[o1] - w * pr);
             // sgn_h * stored + add_h = state - w Tr  ->  stored = sgn_h (state - w Tr - add_h)
-            buf.base[kh] = S(sgn_h * (a.state[o2] - w * Tr - add_h));
+            buf[kh] = S(sgn_h * (a.state[o2] - w * Tr - add_h));
         }
     }
 }
@@ -777,10 +845,12 @@ static hipError_t launch_step_t(const StepArgs& a, int mode, int grid, hipStream
 
 template <class S, class R, bool DEV>
 static hipError_t launch_step_p(const StepArgs& a, int mode, int grid, int tx, int ty, hipStream_t st) {
+    if (tx == 64 && ty == 8) return launch_step_t<64, 8, S, R, DEV>(a, mode, grid, st);
     if (tx == 32 && ty == 8) return launch_step_t<32, 8, S, R, DEV>(a, mode, grid, st);
     if (tx == 64 && ty == 4) return launch_step_t<64, 4, S, R, DEV>(a, mode, grid, st);
     if (tx == 16 && ty == 16) return launch_step_t<16, 16, S, R, DEV>(a, mode, grid, st);
-    if (tx == 64 && ty == 8) return launch_step_t<64, 8, S, R, DEV>(a, mode, grid, st);
+    if (tx == 64 && ty == 16) return launch_step_t<64, 16, S, R, DEV>(a, mode, grid, st);
+    if (tx == 128 && ty == 8) return launch_step_t<128, 8, S, R, DEV>(a, mode, grid, st);
     return hipErrorInvalidValue;
 }
 

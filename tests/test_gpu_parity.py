@@ -74,7 +74,7 @@ def test_ragged_and_tiny_lattices(lbm, shape):
     compare_state(lbm.lbm_get_state(ctx), o.pop)
 
 
-@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (16, 16), (64, 8)])
+@pytest.mark.parametrize("tile", [(64, 8), (32, 8), (64, 4), (16, 16), (64, 16), (128, 8)])
 def test_every_tile_shape(lbm, tile):
     cfg = inputs.perturbed_params(inputs.small_channel(), 5)
     fields = inputs.perturbed_fields(cfg, 5)
@@ -165,21 +165,31 @@ def test_phi_and_mass_conserved_on_gpu(lbm):
 
 
 def test_solve_retires_converged_channel(lbm):
-    """lbm_solve: a channel at rest converges at its second check and stops
-    advancing; the other keeps stepping.  Both match the oracle at their own
-    step counts."""
-    still = inputs.cfg(nx=64, ny=32, b=16.0, dT=0.0)            # isothermal, no flow
-    live = inputs.cfg(nx=64, ny=32, b=16.0, sigma_TT=2e-4)
-    ctx = lbm.lbm_create([still, live])
+    """lbm_solve: a small diffusive channel reaches the tolerance first and
+    stops advancing at its check; the large one keeps stepping.  Both match
+    the oracle at their own step counts, and the retired one's residual at
+    retirement is within the tolerance on the oracle too."""
+    fast = inputs.cfg(nx=16, ny=10, b=5.0, sigma_TT=2e-4, mu_a=0.3, mu_b=0.3, k_a=0.3, k_b=0.3)
+    slow = inputs.cfg(nx=128, ny=64, b=32.0, sigma_TT=2e-4)
+    tol = 1e-6
+    ctx = lbm.lbm_create([fast, slow])
     lbm.lbm_init(ctx)
-    rc, active = lbm.lbm_solve(ctx, 1e-30, 600)
+    rc, active = lbm.lbm_solve(ctx, tol, 3000)
     assert rc == 0 and active == 1
-    r_still = lbm.lbm_residual(ctx, 0)
-    r_live = lbm.lbm_residual(ctx, 1)
-    assert r_still["steps"] == 101
-    assert r_live["steps"] == 600
-    compare_state(lbm.lbm_get_state(ctx, 0), run_oracle(still, 101).pop)
-    compare_state(lbm.lbm_get_state(ctx, 1), run_oracle(live, 600).pop)
+    r_fast = lbm.lbm_residual(ctx, 0)
+    r_slow = lbm.lbm_residual(ctx, 1)
+    s_fast = r_fast["steps"]
+    assert s_fast % 100 == 1 and s_fast < 3000
+    assert r_fast["r"] <= tol
+    assert r_slow["steps"] == 3000 and r_slow["r"] > tol
+    o = run_oracle(fast, s_fast - 101)
+    prev = o.fields()
+    o.step(100)
+    cur = o.fields()
+    assert orc.residual(prev, cur, 100, fast["T_ref"]) <= tol * 1.01
+    o.step(1)
+    compare_state(lbm.lbm_get_state(ctx, 0), o.pop)
+    compare_state(lbm.lbm_get_state(ctx, 1), run_oracle(slow, 3000).pop)
 
 
 def test_full_size_throughput_channel(lbm):
