@@ -15,6 +15,7 @@ which is divergence-free; the tests check that and the boundary conditions.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass
 
 import numpy as np
@@ -225,3 +226,34 @@ def interface_profile(ux: np.ndarray, phi: np.ndarray) -> np.ndarray:
         t = col[j] / (col[j] - col[j + 1])
         out[i] = (1 - t) * ux[j, i] + t * ux[j + 1, i]
     return out
+
+
+def diffuse_interface_velocity(cfg: dict, x=None):
+    """Interface velocity u_x(x, y = 0) of the Sec. 2 solution with the
+    Marangoni stress spread over the diffuse interface as the lattice spreads
+    it: node row y_s of the cold-start tanh profile carries the fraction
+    delta_s = 1.5 W |grad phi|^2 (isotropic y-derivative of the sampled tanh)
+    of the stress, and its response at y = 0 is the sharp solution for an
+    interface at y_s (layers b + y_s and a - y_s).  Exact superposition for
+    equal viscosities and conductivities (the temperature field is then the
+    same harmonic field for every y_s); an estimate otherwise."""
+    ch = channel_from_config(cfg)
+    W = float(cfg["W"])
+    ny, b = int(cfg["ny"]), float(cfg["b"])
+    j = np.arange(-2, ny + 2)
+    y = j - (b - 0.5)
+    phi = 0.5 * (1 + np.tanh(2 * (-y) / W))
+    g = np.zeros_like(phi)
+    g[1:-1] = (phi[2:] - phi[:-2]) / 2
+    ds = 1.5 * W * g ** 2
+    if x is None:
+        x = np.arange(int(cfg["nx"]), dtype=float)
+    x = np.asarray(x, dtype=float)
+    tot = np.zeros_like(x)
+    for k in range(2, len(j) - 2):
+        if ds[k] < 1e-14:
+            continue
+        cs = dataclasses.replace(ch, a=ch.a - y[k], b=ch.b + y[k])
+        u, _ = velocity(cs, x, np.full_like(x, -y[k]))
+        tot += ds[k] * u
+    return tot

@@ -40,8 +40,12 @@ struct lbm_ctx {
     // device memory
     void* popA = nullptr;
     void* popB = nullptr;
-    void* phi0 = nullptr;
+    void* phi0 = nullptr;              // storage reference phi0 by row (float32 mode)
+    void* phir = nullptr;              // zeroth moment of the streamed reference populations minus phi0, by row
+    void* r01 = nullptr;               // their y-moment by row
     void* twall = nullptr;             // bottom-wall temperature by column
+    float* tref = nullptr;             // per-node temperature reference (float32 mode)
+    float* tref_new = nullptr;         // references written by a check step
     double* snap = nullptr;            // 4 * total_nodes
     double* partials = nullptr;        // n_tiles * 8 (capacity for the smallest tile)
     int partial_cap = 0;
@@ -191,6 +195,10 @@ void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
     a.dst_v = parity ? c->popA : c->popB;
     a.phi0_v = c->phi0;
     a.tw_v = c->twall;
+    a.phir_v = c->phir;
+    a.r01_v = c->r01;
+    a.tref_v = c->tref;
+    a.tref_out = c->tref_new;
     for (int k = 0; k < 4; ++k) a.snap[k] = c->snap + (size_t)k * c->total_nodes;
     a.partials = c->partials;
     for (int k = 0; k < 5; ++k) a.out[k] = nullptr;
@@ -214,6 +222,16 @@ int enqueue_step(lbm_ctx* c, long long s) {
         hipError_t e = launch_step(c->prec, a, check ? 1 : 0, grid_of(c->n_tiles), c->tx, c->ty, c->stream);
         if (e != hipSuccess) return fail_hip(c, e, "step kernel launch");
     }
+    if (check && c->prec == LBM_FP32_DEV) {
+        // the check step stored its populations relative to new temperature
+        // references; make those current (before the check may retire a channel)
+        TrefArgs r;
+        r.insts = c->d_inst;
+        r.tref = c->tref;
+        r.tref_new = c->tref_new;
+        hipError_t e = launch_tref_copy(r, c->max_nodes, c->n_inst, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "reference copy launch");
+    }
     if (check) {
         FinArgs f;
         fin_args(c, f);
@@ -221,6 +239,7 @@ int enqueue_step(lbm_ctx* c, long long s) {
         if (e != hipSuccess) return fail_hip(c, e, "check kernel launch");
         e = launch_counter(c->d_counter, CHECK_EVERY, c->stream);
         if (e != hipSuccess) return fail_hip(c, e, "counter kernel launch");
+
     }
     return LBM_OK;
 }
@@ -334,7 +353,6 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         I.kx = 2.0 * M_PI / ((double)p.nx / (double)p.n_waves);
         I.Fx = p.Fx_ext; I.Fy = p.Fy_ext;
         I.p_r = precision == LBM_FP64 ? 0.0 : 1.0 / 3.0;
-        I.T_r = precision == LBM_FP64 ? 0.0 : p.T_ref;
         const long long n = (long long)p.nx * p.ny;
         pop += 27 * n;
         nodes += n;
@@ -357,7 +375,14 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->popA = dev_alloc(c, (size_t)pop * c->elem);
     c->popB = dev_alloc(c, (size_t)pop * c->elem);
     c->phi0 = dev_alloc(c, (size_t)rows * c->elem);
+    c->phir = dev_alloc(c, (size_t)rows * c->elem);
+    c->r01 = dev_alloc(c, (size_t)rows * c->elem);
     c->twall = dev_alloc(c, (size_t)cols * c->elem);
+    if (precision == LBM_FP32_DEV) {
+        c->tref = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
+        c->tref_new = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
+        if (!c->tref || !c->tref_new) rc = LBM_ENOMEM;
+    }
     c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
     c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
     c->d_inst = (Inst*)dev_alloc(c, sizeof(Inst) * n_inst);
@@ -366,29 +391,78 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->d_counter = (long long*)dev_alloc(c, sizeof(long long));
     c->d_tol = (double*)dev_alloc(c, sizeof(double));
     c->d_active = (int*)dev_alloc(c, sizeof(int));
-    if (!c->popA || !c->popB || !c->phi0 || !c->twall || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
+    if (!c->popA || !c->popB || !c->phi0 || !c->phir || !c->r01 || !c->twall || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
         !c->d_res || !c->d_counter || !c->d_tol || !c->d_active) {
         rc = LBM_ENOMEM;
     }
     if (rc == LBM_OK && hipHostMalloc((void**)&c->h_active, sizeof(int), hipHostMallocDefault) != hipSuccess)
         rc = LBM_ENOMEM;
     if (rc == LBM_OK) {
-        // reference rows: cold-start tanh phi0(y) for rows -2 .. ny+1 (float32 mode)
-        std::vector<double> rd(rows);
-        for (int k = 0; k < n_inst; ++k) {
-            const lbm_params& p = params[k];
-            for (int j = -2; j <= p.ny + 1; ++j)
-                rd[c->h_inst[k].row_off + j + 2] =
-                    precision == LBM_FP64 ? 0.0 : 0.5 * (1.0 + std::tanh(2.0 * ((p.b - 0.5) - (double)j) / p.W));
+        // reference rows (float32 mode), rows -2 .. ny+1.  phi0: cold-start
+        // tanh profile, the storage reference (float values).  A node pulls
+        // populations stored relative to w_a phi0(source row) (the source row
+        // of a wall link is the node's own row); dR and r01 are the zeroth
+        // and y-moment of those references, dR taken relative to phi0(row).
+        // dR is rounded to float and then corrected by single ulps until the
+        // float values sum to zero exactly, as the exact values do: the
+        // float32 step then conserves sum phi up to the rounding of small
+        // deviations.
+        std::vector<double> t0(rows, 0.0), tr(rows, 0.0), t1(rows, 0.0);
+        if (precision == LBM_FP32_DEV) {
+            const int EYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+            const double Wh[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+            for (int k = 0; k < n_inst; ++k) {
+                const lbm_params& p = params[k];
+                double* q0 = &t0[c->h_inst[k].row_off + 2];
+                double* qr = &tr[c->h_inst[k].row_off + 2];
+                double* q1 = &t1[c->h_inst[k].row_off + 2];
+                for (int j = -2; j <= p.ny + 1; ++j)
+                    q0[j] = (double)(float)(0.5 * (1.0 + std::tanh(2.0 * ((p.b - 0.5) - (double)j) / p.W)));
+                for (int j = 0; j < p.ny; ++j) {
+                    double s0 = 0.0, s1 = 0.0;
+                    for (int a2 = 0; a2 < 9; ++a2) {
+                        int js = j - EYh[a2];
+                        if (js < 0 || js >= p.ny) js = j;
+                        s0 += Wh[a2] * (q0[js] - q0[j]);
+                        s1 += Wh[a2] * EYh[a2] * q0[js];
+                    }
+                    qr[j] = (double)(float)s0;
+                    q1[j] = s1;
+                }
+                // exact-sum correction of the rounded dR (compensated sum)
+                auto fsum = [&]() {
+                    double s = 0.0, comp = 0.0;
+                    for (int j = 0; j < p.ny; ++j) {
+                        double y = qr[j] - comp, t = s + y;
+                        comp = (t - s) - y;
+                        s = t;
+                    }
+                    return s;
+                };
+                for (int it = 0; it < 4 * p.ny; ++it) {
+                    const double S = fsum();
+                    if (S == 0.0) break;
+                    // adjust the row whose float step best matches the residual
+                    int best = -1;
+                    double bestv = 0.0, bestr = std::fabs(S);
+                    for (int j = 0; j < p.ny; ++j) {
+                        const float o = (float)qr[j];
+                        const float nv = S > 0 ? std::nextafter(o, -INFINITY) : std::nextafter(o, INFINITY);
+                        const double r = std::fabs(S + ((double)nv - (double)o));
+                        if (r < bestr) { bestr = r; best = j; bestv = nv; }
+                    }
+                    if (best < 0) break;
+                    qr[best] = bestv;
+                }
+            }
         }
-        if (precision == LBM_FP64) {
-            if (hipMemcpy(c->phi0, rd.data(), rows * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-                rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
-        } else {
-            std::vector<float> rf(rd.begin(), rd.end());
-            if (hipMemcpy(c->phi0, rf.data(), rows * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
-                rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
-        }
+        auto upload = [&](void* dst, const std::vector<double>& v) -> hipError_t {
+            if (precision == LBM_FP64) return hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+            std::vector<float> f(v.begin(), v.end());
+            return hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+        };
+        if (upload(c->phi0, t0) != hipSuccess || upload(c->phir, tr) != hipSuccess || upload(c->r01, t1) != hipSuccess)
+            rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
     }
     if (rc == LBM_OK) {
         // bottom-wall temperature T_h + dT cos(2 pi i / l) for every column
@@ -472,6 +546,8 @@ int lbm_init(lbm_ctx* c, const double* fields) {
     a.insts = c->d_inst;
     a.dst_v = c->popA;
     a.phi0_v = c->phi0;
+    a.tw_v = c->twall;
+    a.tref = c->tref;
     a.cold = fields ? 0 : 1;
     double* dfields = nullptr;
     if (fields) {
@@ -588,7 +664,6 @@ int lbm_fields(lbm_ctx* c, int32_t inst, double* phi, double* ux, double* uy, do
     I.tile0 = 0;
     set_layout(I, P, c->tx, c->ty);
     I.ntiles = nt;
-    I.node_off = 0;
     I.active = 1;
     Inst* dI = (Inst*)dev_alloc(c, sizeof(Inst));
     int* dT = (int*)dev_alloc(c, sizeof(int) * nt);
@@ -601,7 +676,8 @@ int lbm_fields(lbm_ctx* c, int32_t inst, double* phi, double* ux, double* uy, do
     a.insts = dI;
     a.tile_inst = dT;
     a.n_tiles = nt;
-    for (int k = 0; k < 5; ++k) a.out[k] = out + (size_t)k * n;
+    // the kernel writes at node_off + (j nx + i): shift the output pointers
+    for (int k = 0; k < 5; ++k) a.out[k] = out + (size_t)k * n - I.node_off;
     hipError_t e = launch_step(c->prec, a, 2, grid_of(nt), c->tx, c->ty, c->stream);
     if (e != hipSuccess) return fail_hip(c, e, "fields kernel launch");
     double* dst[5] = {phi, ux, uy, T, p};
@@ -645,6 +721,8 @@ static int state_io(lbm_ctx* c, int32_t inst, double* host, int dir) {
     a.dir = dir;
     a.buf_v = (s & 1) ? c->popB : c->popA;
     a.phi0_v = c->phi0;
+    a.tw_v = c->twall;
+    a.tref = c->tref;
     a.state = d;
     if (dir == 1) HIPCHK(c, hipMemcpyAsync(d, host, sizeof(double) * 27 * n, hipMemcpyHostToDevice, c->stream));
     hipError_t e = launch_state(c->prec, a, (int)n, c->stream);

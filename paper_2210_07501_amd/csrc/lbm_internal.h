@@ -32,7 +32,7 @@ struct Inst {
     double s0, sT, sTT, T_ref;
     double T_h, dT, T_c, kx;      // kx = 2 pi / l
     double Fx, Fy;
-    double p_r, T_r;              // storage references of g and h (0 in float64 mode)
+    double p_r, pad2;             // storage reference of g (0 in float64 mode)
 };
 
 struct Result {
@@ -49,6 +49,10 @@ struct StepArgs {
     void* dst_v;
     const void* phi0_v;           // reference rows (compute type)
     const void* tw_v;             // bottom-wall temperature by column (compute type)
+    const void* phir_v;           // zeroth moment of the streamed reference populations minus phi0, by row
+    const void* r01_v;            // their y-moment, by row
+    const void* tref_v;           // per-node temperature reference (float32 mode)
+    void* tref_out;               // new references written by a check step
     double* snap[4];              // ux, uy, T, phi at the last check
     double* partials;             // [tile][8]
     double* out[5];               // fields: phi, ux, uy, T, p
@@ -67,6 +71,8 @@ struct InitArgs {
     const Inst* insts;
     void* dst_v;
     const void* phi0_v;
+    const void* tw_v;
+    float* tref;
     const double* fields[4];      // phi, ux, uy, T (device), when not cold
     int cold;
 };
@@ -77,7 +83,15 @@ struct StateArgs {
     int dir;                      // 0: buffer -> state, 1: state -> buffer
     void* buf_v;
     const void* phi0_v;
+    const void* tw_v;
+    const float* tref;
     double* state;                // device [3][9][ny][nx] float64
+};
+
+struct TrefArgs {
+    const Inst* insts;
+    float* tref;
+    const float* tref_new;
 };
 
 hipError_t launch_step(int prec, const StepArgs& a, int mode, int grid, int tx, int ty, hipStream_t st);
@@ -86,5 +100,6 @@ hipError_t launch_counter(long long* c, long long n, hipStream_t st);
 hipError_t launch_count_active(const Inst* insts, int n, int* out, hipStream_t st);
 hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, hipStream_t st);
 hipError_t launch_state(int prec, const StateArgs& a, int nodes, hipStream_t st);
+hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStream_t st);
 
 }  // namespace lbm

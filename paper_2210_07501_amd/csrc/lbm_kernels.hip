@@ -19,9 +19,11 @@
 //
 // Storage: per channel, populations [3][9][ny][nx].  In float32 mode the
 // stored numbers are deviations from rest equilibria w_a X_ref with
-// X_ref = phi0(row) for f (the cold-start tanh profile), p_r for g and T_r
-// for h; phi0 is taken at the row of the node that will pull the value.  In
-// float64 mode all references are zero and the numbers are the populations.
+// X_ref = phi0(row) for f (the cold-start tanh profile), p_r for g and a
+// per-node temperature reference for h (moved to the current temperature at
+// every check); each reference is the one of the node that will pull the
+// value.  In float64 mode all references are zero and the numbers are the
+// populations.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -59,17 +61,17 @@ template <class R> struct W9 {
 template <class R> struct P {
     int nx, ny;
     R W, inv_W, M, w_phi, drho, rho_a, mu_a, dmu, k_a, dk;
-    R s0, sT, sTT, dTref;  // dTref = T_r - T_ref
-    R T_h, dT, T_c, kx, Fx, Fy, p_r, T_r;
+    R s0, sT, sTT, Tsig;   // Tsig: T_ref of the surface-tension law
+    R T_h, dT, T_c, kx, Fx, Fy, p_r;
     __device__ void load(const Inst& I) {
         nx = I.nx; ny = I.ny;
         W = R(I.W); inv_W = R(1.0 / I.W); M = R(I.M_phi); w_phi = R(I.w_phi);
         rho_a = R(I.rho_a); drho = R(I.rho_b - I.rho_a);
         mu_a = R(I.mu_a); dmu = R(I.mu_b - I.mu_a);
         k_a = R(I.k_a); dk = R(I.k_b - I.k_a);
-        s0 = R(I.s0); sT = R(I.sT); sTT = R(I.sTT); dTref = R(I.T_r - I.T_ref);
+        s0 = R(I.s0); sT = R(I.sT); sTT = R(I.sTT); Tsig = R(I.T_ref);
         T_h = R(I.T_h); dT = R(I.dT); T_c = R(I.T_c); kx = R(I.kx);
-        Fx = R(I.Fx); Fy = R(I.Fy); p_r = R(I.p_r); T_r = R(I.T_r);
+        Fx = R(I.Fx); Fy = R(I.Fy); p_r = R(I.p_r);
     }
 };
 
@@ -172,11 +174,12 @@ template <class S> struct Pop {
 // Gather the streamed populations of node (i, j) (0 <= j < ny) from the
 // post-collision buffer, with the wall schemes of Sec. 5: g half-way
 // bounce-back, h anti-bounce-back to the wall temperature, f specular
-// (free-slip).  Returned as deviations relative to row j's references.
+// (free-slip).  Returned as deviations relative to the references of node
+// (i, j): phi0 of row j, p_r, and Tro, the node's own temperature reference.
 // NEED: bit 0 f, bit 1 g, bit 2 h.  tw: bottom-wall temperature by column.
 template <class S, class R, int NEED>
 __device__ __forceinline__ void pull_node(const Pop<S>& src, const R* __restrict__ tw, const P<R>& p, int i,
-                                          int j, R* f, R* g, R* h) {
+                                          int j, R Tro, R* f, R* g, R* h) {
     const int nx = p.nx, ny = p.ny;
     const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
     const bool wall_s = j == 0, wall_n = j == ny - 1;
@@ -199,7 +202,7 @@ __device__ __forceinline__ void pull_node(const Pop<S>& src, const R* __restrict
                 if (NEED & 2) g[a] = R(src.ld(1, OPP(a), oi));
                 if (NEED & 4) {
                     const R Tw = (ey > 0) ? tw[i] : p.T_c;
-                    h[a] = -R(src.ld(2, OPP(a), oi)) + R(2) * W9<R>::w(a) * (Tw - p.T_r);
+                    h[a] = -R(src.ld(2, OPP(a), oi)) + R(2) * W9<R>::w(a) * (Tw - Tro);
                 }
             }
         }
@@ -246,17 +249,20 @@ __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
 #endif
 void step_kernel(StepArgs a) {
     constexpr int NT = TX * TY;
-    constexpr int LX2 = TX + 4, LY2 = TY + 4;   // phi region (halo 2)
+    constexpr int LX2 = TX + 4, LY2 = TY + 4;   // phi and T-reference region (halo 2)
     constexpr int LX1 = TX + 2, LY1 = TY + 2;   // T, p*, n region (halo 1)
     constexpr int RING = LX2 * LY2 - TX * TY;
 
-    __shared__ R s_phb[LY2 * LX2];
-    __shared__ R s_Tb[LY1 * LX1];
-    __shared__ R s_pb[LY1 * LX1];
+    __shared__ R s_phb[LY2 * LX2];  // phi - phi0(row)
+    __shared__ R s_Tr[LY2 * LX2];   // temperature reference (float32 mode)
+    __shared__ R s_Tb[LY1 * LX1];   // T - Tr
+    __shared__ R s_pb[LY1 * LX1];   // p* - p_r
     __shared__ R s_nx[LY1 * LX1];
-    __shared__ R s_dny[LY1 * LX1];
-    __shared__ R s_phi0[LY2];     // reference phi0 of rows y0-2 .. y0+TY+1
-    __shared__ R s_n0y[LY1];      // reference normal of rows y0-1 .. y0+TY
+    __shared__ R s_dny[LY1 * LX1];  // n_y - n0_y
+    __shared__ R s_phi0[LY2];       // storage reference phi0 of rows y0-2 .. y0+TY+1
+    __shared__ R s_dR[LY2];         // phi of the streamed reference populations minus phi0, same rows
+    __shared__ R s_r01[LY2];        // their y-moment
+    __shared__ R s_n0y[LY1];        // reference normal of rows y0-1 .. y0+TY
     __shared__ double s_red[(NT / 64) * 8];
 
     // XCD-aware mapping: consecutive tiles share an XCD (and its L2)
@@ -288,15 +294,28 @@ void step_kernel(StepArgs a) {
     }
     const int x0 = tcol * TX, y0 = trow * TY;
 
-    const R* phi0t = (const R*)a.phi0_v;
     Pop<S> src{(S*)a.src_v + I.pop_off, (uint32_t)nx * (uint32_t)ny};
     const R* __restrict__ tw = (const R*)a.tw_v + I.col_off;
     const int tid = threadIdx.x;
+    auto colwrap = [&](int ii) {
+        ii = ii < 0 ? ii + nx : ii;
+        return ii >= nx ? ((ii - nx < nx) ? ii - nx : modx(ii, nx)) : ii;
+    };
 
-    // reference rows
+    // ---- phase 0: reference rows and temperature references ---------------
     for (int k = tid; k < LY2; k += NT) {
-        const int gj = y0 - 2 + k;
-        s_phi0[k] = DEV ? phi0t[I.row_off + min(max(gj, -2), ny + 1) + 2] : R(0);
+        const int r = I.row_off + min(max(y0 - 2 + k, -2), ny + 1) + 2;
+        s_phi0[k] = DEV ? ((const R*)a.phi0_v)[r] : R(0);
+        s_dR[k] = DEV ? ((const R*)a.phir_v)[r] : R(0);
+        s_r01[k] = DEV ? ((const R*)a.r01_v)[r] : R(0);
+    }
+    if (DEV) {
+        const R* __restrict__ tref = (const R*)a.tref_v + I.node_off;
+        for (int k = tid; k < LY2 * LX2; k += NT) {
+            const int hy = k / LX2 - 2, hx = k % LX2 - 2;
+            const int jj = y0 + hy;
+            s_Tr[k] = (jj >= 0 && jj < ny) ? tref[(uint32_t)jj * (uint32_t)nx + (uint32_t)colwrap(x0 + hx)] : R(0);
+        }
     }
     __syncthreads();
     for (int k = tid; k < LY1; k += NT) {
@@ -304,19 +323,51 @@ void step_kernel(StepArgs a) {
         const R g0 = R(0.5) * (s_phi0[k + 2] - s_phi0[k]);
         s_n0y[k] = DEV ? g0 / sqrt(g0 * g0 + R(EPS_N * EPS_N)) : R(0);
     }
+    // Temperature-reference moments of the populations streamed into node
+    // (hx, hy): each is stored relative to its writer's reference, so the
+    // node sees sum_a w_a e_a^m (Tr(source) - Tr(node)) on top of its own.
+    auto tcorr = [&](int hx, int hy, int jj, R& c0, R& cx, R& cy) {
+        c0 = R(0); cx = R(0); cy = R(0);
+        const R t0 = s_Tr[(hy + 2) * LX2 + hx + 2];
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+            const int ex = EX(q), ey = EY(q);
+            if (ey != 0 && (jj - ey < 0 || jj - ey >= ny)) continue;   // wall link
+            const R d = W9<R>::w(q) * (s_Tr[(hy - ey + 2) * LX2 + hx - ex + 2] - t0);
+            c0 += d;
+            if (ex) cx += ex > 0 ? d : -d;
+            if (ey) cy += ey > 0 ? d : -d;
+        }
+    };
 
-    // ---- phase 1: pull own node (27 values kept) and the halo ring --------
+    // ---- phase 1: pull own node and the halo ring ---------------------------
     const int tx = tid % TX, ty = tid / TX;
     const int gi = (x0 + tx < nx) ? x0 + tx : modx(x0 + tx, nx), gj = y0 + ty;
     const bool own_row = gj < ny;
     const bool own_ok = own_row && (x0 + tx < nx);
     R f[9], g[9], h[9];
     R rf[9], rg[9], rh[9];
+    const R Tro = DEV ? s_Tr[(ty + 2) * LX2 + tx + 2] : R(0);   // this node's T reference
+    double dph_d = 0.0;   // float32 mode: phi - phi0(row), accumulated in float64
     if (own_row) {
-        pull_node<S, R, 7>(src, tw, p, gi, gj, f, g, h);
+        pull_node<S, R, 7>(src, tw, p, gi, gj, Tro, f, g, h);
         raw_moments(f, rf);
         raw_moments(g, rg);
         raw_moments(h, rh);
+        if (DEV) {
+            R c0, cx, cy;
+            tcorr(tx, ty, gj, c0, cx, cy);
+            rh[0] += c0;
+            rh[3] += cx;
+            rh[1] += cy;
+            rf[1] += s_r01[ty + 2];
+            // phi - phi0(row), summed in float64 so that the step conserves
+            // sum phi up to the rounding of one small stored value
+            dph_d = (double)s_dR[ty + 2];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) dph_d += (double)f[q];
+            rf[0] = (R)dph_d;
+        }
         s_phb[(ty + 2) * LX2 + tx + 2] = rf[0];
         s_pb[(ty + 1) * LX1 + tx + 1] = rg[0];
         s_Tb[(ty + 1) * LX1 + tx + 1] = rh[0];
@@ -328,24 +379,30 @@ void step_kernel(StepArgs a) {
         else { int q = k - 4 * LX2; hy = q / 4; int c = q % 4; hx = c < 2 ? c - 2 : TX + c - 2; }
         const int jj = y0 + hy;
         if (jj < 0 || jj >= ny) continue;
-        int ii = x0 + hx;
-        ii = ii < 0 ? ii + nx : ii;
-        ii = ii >= nx ? ((ii - nx < nx) ? ii - nx : modx(ii, nx)) : ii;
+        const int ii = colwrap(x0 + hx);
         const bool h1 = hx >= -1 && hx <= TX && hy >= -1 && hy <= TY;
         R tf[9], tg[9], th[9];
         if (h1) {
-            pull_node<S, R, 7>(src, tw, p, ii, jj, tf, tg, th);
+            const R Trr = DEV ? s_Tr[(hy + 2) * LX2 + hx + 2] : R(0);
+            pull_node<S, R, 7>(src, tw, p, ii, jj, Trr, tf, tg, th);
             R s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) { s1 += tf[q]; s2 += tg[q]; s3 += th[q]; }
+            if (DEV) {
+                R c0, cx, cy;
+                tcorr(hx, hy, jj, c0, cx, cy);
+                s3 += c0;
+                s1 += s_dR[hy + 2];
+            }
             s_phb[(hy + 2) * LX2 + hx + 2] = s1;
             s_pb[(hy + 1) * LX1 + hx + 1] = s2;
             s_Tb[(hy + 1) * LX1 + hx + 1] = s3;
         } else {
-            pull_node<S, R, 1>(src, tw, p, ii, jj, tf, tg, th);
+            pull_node<S, R, 1>(src, tw, p, ii, jj, R(0), tf, tg, th);
             R s1 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) s1 += tf[q];
+            if (DEV) s1 += s_dR[hy + 2];
             s_phb[(hy + 2) * LX2 + hx + 2] = s1;
         }
     }
@@ -360,21 +417,21 @@ void step_kernel(StepArgs a) {
         const int mhy = mj - y0;
         const bool valid = (jj >= -2 && jj <= ny + 1) && mhy >= -2 && mhy <= TY + 1;
         R v = R(0);
-        if (valid) {
-            v = s_phb[(mhy + 2) * LX2 + hx + 2] + (s_phi0[mhy + 2] - s_phi0[hy + 2]);
-        }
-        s_phb[(hy + 2) * LX2 + hx + 2] = v;
+        if (valid) v = s_phb[(mhy + 2) * LX2 + hx + 2] + (s_phi0[mhy + 2] - s_phi0[hy + 2]);
+        s_phb[k] = v;
         if (hx >= -1 && hx <= TX && hy >= -1 && hy <= TY) {
-            R vp = R(0), vT = R(0);
+            R vp = R(0), vT = R(0), vr = R(0);
             if (valid && (jj == -1 || jj == ny)) {
                 vp = s_pb[(mhy + 1) * LX1 + hx + 1];
                 const R Tm = s_Tb[(mhy + 1) * LX1 + hx + 1];
-                const int ii = modx(x0 + hx, nx);
-                const R Tw = (jj < 0) ? tw[ii] : p.T_c;
-                vT = R(2) * (Tw - p.T_r) - Tm;
+                vr = DEV ? s_Tr[(mhy + 2) * LX2 + hx + 2] : R(0);   // ghost reference := mirror's
+                const R Tw = (jj < 0) ? tw[colwrap(x0 + hx)] : p.T_c;
+                // T_ghost = 2 T_w - T_mirror; deviation from vr formed exactly
+                vT = R(2.0 * ((double)Tw - (double)vr)) - Tm;
             }
             s_pb[(hy + 1) * LX1 + hx + 1] = vp;
             s_Tb[(hy + 1) * LX1 + hx + 1] = vT;
+            if (DEV) s_Tr[k] = vr;
         }
     }
     __syncthreads();
@@ -439,19 +496,25 @@ void step_kernel(StepArgs a) {
         grad(s_nx, c1, LX1, dnx_dx, dnx_dy);
         grad(s_dny, c1, LX1, ddy_dx, ddy_dy);
         const R curv = dnx_dx + ddy_dy + R(0.5) * (s_n0y[ty + 2] - s_n0y[ty]);
-        // surface tension from the stencil temperatures (Eq. ST_SRF), less sigma0
-        R sg[9];
-        {
-            const int offs[9] = {0, 1, LX1, -1, -LX1, LX1 + 1, LX1 - 1, -LX1 - 1, -LX1 + 1};
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                const R d = s_Tb[c1 + offs[q]] + p.dTref;
-                sg[q] = (p.sT + p.sTT * d) * d;
-            }
-        }
-        const R dsx = (sg[1] - sg[3]) * (R(1) / R(3)) + (sg[5] - sg[6] + sg[8] - sg[7]) * (R(1) / R(12));
-        const R dsy = (sg[2] - sg[4]) * (R(1) / R(3)) + (sg[5] + sg[6] - sg[8] - sg[7]) * (R(1) / R(12));
-        const R sig = p.s0 + sg[0];
+        // surface tension (Eq. ST_SRF) and its isotropic gradient.  Each
+        // stencil difference sigma(T1) - sigma(T2) is formed as
+        // (T1 - T2) (s_T + s_TT (d1 + d2)), d = T - T_ref, with T1 - T2 taken
+        // as (reference difference) + (deviation difference): exact up to
+        // the rounding of the small deviations.
+        // the temperature reference is zero in float64 mode (s_Tr unused)
+        auto Tr_at = [&](int dx, int dy) { return DEV ? s_Tr[c2 + dy * LX2 + dx] : R(0); };
+        auto Tb_at = [&](int dx, int dy) { return s_Tb[c1 + dy * LX1 + dx]; };
+        auto dref = [&](int dx, int dy) { return (Tr_at(dx, dy) - p.Tsig) + Tb_at(dx, dy); };
+        auto dsig = [&](int x1, int y1, int x2, int y2) {
+            const R dT12 = (Tr_at(x1, y1) - Tr_at(x2, y2)) + (Tb_at(x1, y1) - Tb_at(x2, y2));
+            return dT12 * (p.sT + p.sTT * (dref(x1, y1) + dref(x2, y2)));
+        };
+        const R dsx = dsig(1, 0, -1, 0) * (R(1) / R(3)) +
+                      (dsig(1, 1, -1, 1) + dsig(1, -1, -1, -1)) * (R(1) / R(12));
+        const R dsy = dsig(0, 1, 0, -1) * (R(1) / R(3)) +
+                      (dsig(1, 1, 1, -1) + dsig(-1, 1, -1, -1)) * (R(1) / R(12));
+        const R d0 = dref(0, 0);
+        const R sig = p.s0 + (p.sT + p.sTT * d0) * d0;
         R dpx, dpy;
         grad(s_pb, c1, LX1, dpx, dpy);
         // CSF force (Sec. 3): 1.5 W |grad phi|^2 [ -sigma kappa n + (I - n n) grad sigma ]
@@ -471,7 +534,7 @@ void step_kernel(StepArgs a) {
         const R uy = (rg[1] + R(0.5) * cs2 * Fty) * (R(3) * rrho);
         const R Gam = Fpx * ux + Fpy * uy;
         const R pb = rg[0] + R(0.5) * Gam;          // p - p_r
-        const R Tb = rh[0];                          // T - T_r
+        R Tb = rh[0];                                // T - Tro
 
         if (MODE == 2) {
             if (own_ok) {
@@ -479,29 +542,41 @@ void step_kernel(StepArgs a) {
                 a.out[0][q] = (double)phi;
                 a.out[1][q] = (double)ux;
                 a.out[2][q] = (double)uy;
-                a.out[3][q] = (double)p.T_r + (double)Tb;
+                a.out[3][q] = (double)Tro + (double)Tb;
                 a.out[4][q] = (double)p.p_r + (double)pb;
             }
         } else {
-            if (MODE == 1 && own_ok) {
-                const size_t q = (size_t)I.node_off + (size_t)gj * nx + gi;
-                const double dux = (double)ux, duy = (double)uy;
-                const double dT = (double)Tb + (double)p.dTref;   // T - T_ref
-                const double Tfull = (double)p.T_r + (double)Tb;
-                const double o_ux = a.snap[0][q], o_uy = a.snap[1][q], o_T = a.snap[2][q];
-                red[0] = (dux - o_ux) * (dux - o_ux) + (duy - o_uy) * (duy - o_uy);
-                red[1] = dux * dux + duy * duy;
-                red[2] = (Tfull - o_T) * (Tfull - o_T);
-                red[3] = dT * dT;
-                red[4] = (double)phi;
-                red[5] = (double)rho;
-                const bool bad = !(isfinite(dux) && isfinite(duy) && isfinite(Tfull) && isfinite((double)phi) &&
-                                   isfinite((double)pb));
-                red[6] = bad ? 1.0 : 0.0;
-                a.snap[0][q] = dux;
-                a.snap[1][q] = duy;
-                a.snap[2][q] = Tfull;
-                a.snap[3][q] = (double)phi;
+            R Tr = Tro;
+            if (MODE == 1) {
+                if (own_ok) {
+                    const size_t q = (size_t)I.node_off + (size_t)gj * nx + gi;
+                    const double dux = (double)ux, duy = (double)uy;
+                    const double Tfull = (double)Tro + (double)Tb;
+                    const double dT = ((double)Tro - I.T_ref) + (double)Tb;   // T - T_ref
+                    const double o_ux = a.snap[0][q], o_uy = a.snap[1][q], o_T = a.snap[2][q];
+                    red[0] = (dux - o_ux) * (dux - o_ux) + (duy - o_uy) * (duy - o_uy);
+                    red[1] = dux * dux + duy * duy;
+                    red[2] = (Tfull - o_T) * (Tfull - o_T);
+                    red[3] = dT * dT;
+                    red[4] = (double)phi;
+                    red[5] = (double)rho;
+                    const bool bad = !(isfinite(dux) && isfinite(duy) && isfinite(Tfull) &&
+                                       isfinite((double)phi) && isfinite((double)pb));
+                    red[6] = bad ? 1.0 : 0.0;
+                    a.snap[0][q] = dux;
+                    a.snap[1][q] = duy;
+                    a.snap[2][q] = Tfull;
+                    a.snap[3][q] = (double)phi;
+                }
+                if (DEV) {
+                    // move this node's temperature reference to its current
+                    // temperature: the values written below are stored
+                    // relative to it (the next steps read the new references)
+                    const R Tn = Tro + Tb;
+                    Tb = Tb - (Tn - Tro);
+                    Tr = Tn;
+                    if (own_ok) ((R*)a.tref_out)[(size_t)I.node_off + (size_t)gj * nx + gi] = Tn;
+                }
             }
             // local relaxation rates
             const R mu = p.mu_a + phi * p.dmu, kc = p.k_a + phi * p.dk;
@@ -510,30 +585,40 @@ void step_kernel(StepArgs a) {
             const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
 
             // --- ACE (Sec. 4.1): relax first central moments to M theta n ---
+            // stored as f - w phi0(row of this node)
             {
                 const R ph0 = s_phi0[ty + 2];
+                const R dph = phb;                                // phi - phi0
                 const R theta = R(4) * phi * (R(1) - phi) * p.inv_W;
                 const R k10 = rf[3] - ux * phi, k01 = rf[1] - uy * phi;
                 const R t10 = k10 + p.w_phi * (p.M * theta * nxv - k10);
                 const R t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
                 // post-collision central moments minus ph0 * (rest central moments)
                 R c[9];
-                c[0] = phb;                                  // 00
+                c[0] = dph;                                  // 00
                 c[1] = t01 + ph0 * uy;                       // 01
-                c[2] = phb * cs2 - ph0 * uy2;                // 02
+                c[2] = dph * cs2 - ph0 * uy2;                // 02
                 c[3] = t10 + ph0 * ux;                       // 10
                 c[4] = -ph0 * uxy;                           // 11
                 c[5] = ph0 * ux * (cs2 + uy2);               // 12
-                c[6] = phb * cs2 - ph0 * ux2;                // 20
+                c[6] = dph * cs2 - ph0 * ux2;                // 20
                 c[7] = ph0 * uy * (cs2 + ux2);               // 21
-                c[8] = phb * (cs2 * cs2) - ph0 * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
+                c[8] = dph * (cs2 * cs2) - ph0 * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
                 central_to_raw(c, ux, uy);
                 raw_to_dist(c, f);
+                if (DEV) {
+                    // the rest population takes the rounding of the other
+                    // eight: the stored values sum to phi - phi0 in float64
+                    double s8 = 0.0;
+#pragma unroll
+                    for (int q = 1; q < 9; ++q) s8 += (double)f[q];
+                    f[0] = (R)(dph_d - s8);
+                }
             }
-            // --- energy (Sec. 4.3) ---
+            // --- energy (Sec. 4.3), stored as h - w Tr(this node) ---
             {
-                const R Tr = p.T_r;
-                const R c10 = rh[3] - ux * (Tr + Tb), c01 = rh[1] - uy * (Tr + Tb);
+                const R T = Tro + rh[0];
+                const R c10 = rh[3] - ux * T, c01 = rh[1] - uy * T;
                 R c[9];
                 c[0] = Tb;
                 c[1] = c01 * (R(1) - w_T) + Tr * uy;
@@ -547,7 +632,7 @@ void step_kernel(StepArgs a) {
                 central_to_raw(c, ux, uy);
                 raw_to_dist(c, h);
             }
-            // --- hydrodynamics (Sec. 4.2) ---
+            // --- hydrodynamics (Sec. 4.2), stored as g - w p_r ---
             {
                 const R pr = p.p_r;
                 const R vphi = pb + (pr - rho * cs2);     // p - rho c_s^2
@@ -560,7 +645,6 @@ void step_kernel(StepArgs a) {
                 const R s20 = R(2) * cs2 * Fpx * ux + (ux2 + cs2) * Gam;
                 const R s02 = R(2) * cs2 * Fpy * uy + (uy2 + cs2) * Gam;
                 const R s11 = cs2 * (Fpx * uy + Fpy * ux) + uxy * Gam;
-                // equilibria (deviation parts computed below)
                 const R q2d = vphi * (ux2 - uy2), q11 = vphi * uxy;
                 const R t2d = e2d + w_nu * (q2d - e2d) + (R(1) - R(0.5) * w_nu) * (s20 - s02);
                 const R t11 = e11 + w_nu * (q11 - e11) + (R(1) - R(0.5) * w_nu) * s11;
@@ -583,22 +667,9 @@ void step_kernel(StepArgs a) {
             }
             if (own_ok) {
                 Pop<S> dst{(S*)a.dst_v + I.pop_off, (uint32_t)nx * (uint32_t)ny};
-                const uint32_t off = (uint32_t)gj * (uint32_t)nx + (uint32_t)gi;
-                if (DEV) {
-                    // f deviations relative to the row of the node that pulls them
-                    const R ph0 = s_phi0[ty + 2];
-#pragma unroll
-                    for (int q = 1; q < 9; ++q) {
-                        const int ey = EY(q);
-                        if (ey == 0) continue;
-                        const int jr = gj + ey;
-                        const R phr = (jr >= 0 && jr < ny) ? s_phi0[ty + 2 + ey] : ph0;
-                        f[q] += W9<R>::w(q) * (ph0 - phr);
-                    }
-                }
+                const uint32_t bo = ((uint32_t)gj * (uint32_t)nx + (uint32_t)gi) * (uint32_t)sizeof(S);
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    const uint32_t bo = off * (uint32_t)sizeof(S);
                     store_pop((S*)((char*)dst.plane(0, q) + bo), S(f[q]));
                     store_pop((S*)((char*)dst.plane(1, q) + bo), S(g[q]));
                     store_pop((S*)((char*)dst.plane(2, q) + bo), S(h[q]));
@@ -704,6 +775,22 @@ __global__ void count_active_kernel(const Inst* insts, int n, int* out) {
 }
 
 // ---------------------------------------------------------------------------
+// Storage convention (float32 mode).  The value a node writes for direction
+// k is stored relative to that writer's own references: w_k phi0(row), w_k
+// p_r, w_k Tr(writer).  The node that pulls it (the neighbour at +e_k, or
+// the writer itself through a wall link) adds them back.  In float64 mode all
+// references are zero.
+
+// Temperature of node (i, j) from the init fields (cold start or given).
+template <class R>
+__device__ __forceinline__ double init_T_src(const InitArgs& a, const Inst& I, int i, int j, const R* tw) {
+    if (a.cold) {
+        const double Tb = (double)tw[i];
+        return Tb + (I.T_c - Tb) * ((double)j + 0.5) / (double)I.ny;
+    }
+    return a.fields[3][(size_t)I.node_off + (size_t)j * I.nx + i];
+}
+
 // Equilibrium state from fields, written into the post-collision buffer so
 // that the next gather yields it (inverse of the gather, walls included).
 template <class S, class R, bool DEV>
@@ -716,42 +803,34 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     if (q >= n) return;
     const int i = (int)(q % nx), j = (int)(q / nx);
     const double cs2 = 1.0 / 3.0;
-    double phi, ux, uy, T;
+    // wall temperatures as the step kernel sees them
+    const R* twr = (const R*)a.tw_v + I.col_off;
+    auto tw_at = [&](int ii) { return (double)twr[ii]; };
+    double phi, ux, uy;
     if (a.cold) {
         // fluid at rest, tanh interface at y = b - 1/2, T linear between walls
         phi = 0.5 * (1.0 + tanh(2.0 * ((I.b - 0.5) - (double)j) / I.W));
         ux = 0.0;
         uy = 0.0;
-        const double Tb = I.T_h + I.dT * cos(I.kx * (double)i);
-        T = Tb + (I.T_c - Tb) * ((double)j + 0.5) / (double)ny;
     } else {
         const size_t o = (size_t)I.node_off + (size_t)q;
         phi = a.fields[0][o];
         ux = a.fields[1][o];
         uy = a.fields[2][o];
-        T = a.fields[3][o];
+    }
+    double T;
+    if (a.cold) {
+        const double Tb = tw_at(i);
+        T = Tb + (I.T_c - Tb) * ((double)j + 0.5) / (double)ny;
+    } else {
+        T = a.fields[3][(size_t)I.node_off + (size_t)q];
     }
     const double rho = I.rho_a + phi * (I.rho_b - I.rho_a);
     const double p0 = 1.0 / 3.0;
     const double vphi = p0 - rho * cs2;
     const double ux2 = ux * ux, uy2 = uy * uy;
-    // central-moment equilibria; reference rest moments subtracted (DEV)
-    const double ph0 = DEV ? (double)((const R*)a.phi0_v)[I.row_off + j + 2] : 0.0;
-    const double pr = DEV ? I.p_r : 0.0, Tr = DEV ? I.T_r : 0.0;
+    // absolute equilibria from their central moments (order [mx*3+my])
     double cf[9], cg[9], ch[9];
-    // order [mx*3+my]
-    auto rest_central = [&](double X, double* c, double sc) {
-        // add sc * X * (central moments about u of the rest equilibrium)
-        c[0] += sc * X;
-        c[1] += sc * X * (-uy);
-        c[2] += sc * X * (cs2 + uy2);
-        c[3] += sc * X * (-ux);
-        c[4] += sc * X * (ux * uy);
-        c[5] += sc * X * (-ux * (cs2 + uy2));
-        c[6] += sc * X * (cs2 + ux2);
-        c[7] += sc * X * (-uy * (cs2 + ux2));
-        c[8] += sc * X * (cs2 + ux2) * (cs2 + uy2);
-    };
     for (int k = 0; k < 9; ++k) { cf[k] = 0; cg[k] = 0; ch[k] = 0; }
     cf[0] = phi; cf[2] = cs2 * phi; cf[6] = cs2 * phi; cf[8] = cs2 * cs2 * phi;
     ch[0] = T; ch[2] = cs2 * T; ch[6] = cs2 * T; ch[8] = cs2 * cs2 * T;
@@ -759,30 +838,36 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     cg[6] = p0 * cs2 + vphi * ux2; cg[2] = p0 * cs2 + vphi * uy2; cg[4] = vphi * ux * uy;
     cg[7] = -vphi * (ux2 + cs2) * uy; cg[5] = -vphi * (uy2 + cs2) * ux;
     cg[8] = cs2 * cs2 * cs2 * rho + vphi * (ux2 + cs2) * (uy2 + cs2);
-    rest_central(ph0, cf, -1.0);
-    rest_central(pr, cg, -1.0);
-    rest_central(Tr, ch, -1.0);
     double ef[9], eg[9], eh[9];
     central_to_raw(cf, ux, uy); raw_to_dist(cf, ef);
     central_to_raw(cg, ux, uy); raw_to_dist(cg, eg);
     central_to_raw(ch, ux, uy); raw_to_dist(ch, eh);
+    const R* phi0 = (const R*)a.phi0_v + I.row_off + 2;
+    const double pr = DEV ? I.p_r : 0.0;
+    if (DEV) a.tref[I.node_off + q] = (float)T;
+    const double Tr_self = DEV ? (double)(float)T : 0.0;
     S* dst = (S*)a.dst_v + I.pop_off;
-    // inverse gather: the value that node (i, j) will pull for direction k
+    // inverse gather: the value that node (i, j) will pull for direction k,
+    // relative to the references of its writer
     for (int k = 0; k < 9; ++k) {
         const int ex = EX(k), ey = EY(k);
         const int js = j - ey;
         const int is = wrapx(i - ex, nx);
         const double w = W9<double>::w(k);
         if (js >= 0 && js < ny) {
-            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k]);
-            dst[pidx(nx, ny, 1, k, js, is)] = S(eg[k]);
-            dst[pidx(nx, ny, 2, k, js, is)] = S(eh[k]);
+            const double ph_w = DEV ? (double)phi0[js] : 0.0;
+            const double T_w = DEV ? (double)(float)init_T_src(a, I, is, js, twr) : 0.0;
+            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k] - w * ph_w);
+            dst[pidx(nx, ny, 1, k, js, is)] = S(eg[k] - w * pr);
+            dst[pidx(nx, ny, 2, k, js, is)] = S(eh[k] - w * T_w);
         } else {
             const int mir = MIRY(k), opp = OPP(k);
-            const double Tw = (ey > 0) ? I.T_h + I.dT * cos(I.kx * (double)i) : I.T_c;
-            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k]);
-            dst[pidx(nx, ny, 1, opp, j, i)] = S(eg[k]);
-            dst[pidx(nx, ny, 2, opp, j, i)] = S(2.0 * w * (Tw - Tr) - eh[k]);
+            const double Tw = (ey > 0) ? tw_at(i) : I.T_c;
+            const double ph_w = DEV ? (double)phi0[j] : 0.0;
+            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k] - w * ph_w);
+            dst[pidx(nx, ny, 1, opp, j, i)] = S(eg[k] - w * pr);
+            // anti-bounce-back: h_k = -(stored + w Tr_self) + 2 w T_w
+            dst[pidx(nx, ny, 2, opp, j, i)] = S(2.0 * w * Tw - w * Tr_self - eh[k]);
         }
     }
 }
@@ -797,8 +882,11 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     const int i = (int)(q % nx), j = (int)(q / nx);
-    const double ph0 = DEV ? (double)((const float*)a.phi0_v)[I.row_off + j + 2] : 0.0;
-    const double pr = DEV ? I.p_r : 0.0, Tr = DEV ? I.T_r : 0.0;
+    const S* phi0 = (const S*)a.phi0_v + I.row_off + 2;
+    const S* tw = (const S*)a.tw_v + I.col_off;
+    const float* tref = a.tref ? a.tref + I.node_off : nullptr;
+    const double pr = DEV ? I.p_r : 0.0;
+    const double Tr_self = DEV ? (double)tref[q] : 0.0;
     S* buf = (S*)a.buf_v + I.pop_off;
     for (int k = 0; k < 9; ++k) {
         const int ex = EX(k), ey = EY(k);
@@ -806,30 +894,47 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
         const int is = wrapx(i - ex, nx);
         const double w = W9<double>::w(k);
         size_t kf, kg, kh;
-        double sgn_h = 1.0, add_h = 0.0;
+        double ref_f, ref_h, sgn_h = 1.0, add_h = 0.0;
         if (js >= 0 && js < ny) {
             kf = pidx(nx, ny, 0, k, js, is); kg = pidx(nx, ny, 1, k, js, is); kh = pidx(nx, ny, 2, k, js, is);
+            ref_f = DEV ? w * (double)phi0[js] : 0.0;
+            ref_h = DEV ? w * (double)tref[(size_t)js * nx + is] : 0.0;
         } else {
             const int mir = MIRY(k), opp = OPP(k);
-            const double Tw = (ey > 0) ? I.T_h + I.dT * cos(I.kx * (double)i) : I.T_c;
+            const double Tw = (ey > 0) ? (double)tw[i] : I.T_c;
             kf = pidx(nx, ny, 0, mir, j, is); kg = pidx(nx, ny, 1, opp, j, i); kh = pidx(nx, ny, 2, opp, j, i);
+            ref_f = DEV ? w * (double)phi0[j] : 0.0;
+            // h_k = -(stored + w Tr_self) + 2 w T_w
             sgn_h = -1.0;
-            add_h = 2.0 * w * (Tw - Tr);
+            ref_h = 0.0;
+            add_h = 2.0 * w * Tw - w * Tr_self;
         }
         const size_t o0 = ((size_t)(0 * 9 + k) * ny + j) * nx + i;
         const size_t o1 = ((size_t)(1 * 9 + k) * ny + j) * nx + i;
         const size_t o2 = ((size_t)(2 * 9 + k) * ny + j) * nx + i;
         if (a.dir == 0) {
-            a.state[o0] = w * ph0 + (double)buf[kf];
+            a.state[o0] = ref_f + (double)buf[kf];
             a.state[o1] = w * pr + (double)buf[kg];
-            a.state[o2] = w * Tr + sgn_h * (double)buf[kh] + add_h;
+            a.state[o2] = sgn_h * (double)buf[kh] + ref_h + add_h;
         } else {
-            buf[kf] = S(a.state[o0] - w * ph0);
+            buf[kf] = S(a.state[o0] - ref_f);
             buf[kg] = S(a.state[o1] - w * pr);
-            // sgn_h * stored + add_h = state - w Tr  ->  stored = sgn_h (state - w Tr - add_h)
-            buf[kh] = S(sgn_h * (a.state[o2] - w * Tr - add_h));
+            buf[kh] = S(sgn_h * (a.state[o2] - ref_h - add_h));
         }
     }
+}
+
+// Float32 mode: after a check step, the step kernel has stored this step's
+// populations relative to new temperature references (written to a second
+// array); make them current.  Channels that were active in that step only.
+__global__ __launch_bounds__(256) void tref_copy_kernel(TrefArgs a) {
+    const int inst = blockIdx.y;
+    const Inst& I = a.insts[inst];
+    if (!I.active) return;
+    const long long n = (long long)I.nx * I.ny;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    a.tref[I.node_off + q] = a.tref_new[I.node_off + q];
 }
 
 // ---------------------------------------------------------------------------
@@ -878,6 +983,11 @@ hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, h
     dim3 g((max_nodes + 255) / 256, n_inst), b(256);
     if (prec == 0) hipLaunchKernelGGL((init_kernel<double, double, false>), g, b, 0, st, a);
     else hipLaunchKernelGGL((init_kernel<float, float, true>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(tref_copy_kernel, dim3((max_nodes + 255) / 256, n_inst), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

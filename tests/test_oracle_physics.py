@@ -11,8 +11,6 @@ Which mistake each pin catches (one line each):
   Laplace pressure          capillary term -sigma kappa n, delta_s = 1.5 W |grad phi|^2
   NF / SRF vs Sec. 2        Marangoni term, dsigma/dT, roll count and flow direction
 """
-import dataclasses
-
 import numpy as np
 import pytest
 
@@ -143,31 +141,6 @@ def test_laplace_pressure_of_static_drop():
     assert 0.85 < dp / (s0 / R) < 1.0
 
 
-def diffuse_interface_prediction(c, W):
-    """Sec. 2 solution superposed over the discrete delta_s of the lattice:
-    each node row y_s of the diffuse interface carries the fraction delta_s
-    of the Marangoni stress; its velocity response at y = 0 is the sharp
-    solution for an interface at y_s (layers b + y_s, a - y_s; the
-    temperature there is the same harmonic field since k~ = 1)."""
-    ch = an.channel_from_config(c)
-    ny, b = int(c["ny"]), float(c["b"])
-    j = np.arange(-2, ny + 2)
-    y = j - (b - 0.5)
-    phi = 0.5 * (1 + np.tanh(2 * (-y) / W))
-    g = np.zeros_like(phi)
-    g[1:-1] = (phi[2:] - phi[:-2]) / 2
-    ds = 1.5 * W * g ** 2
-    x = np.arange(int(c["nx"]), dtype=float)
-    tot = np.zeros_like(x)
-    for k in range(2, len(j) - 2):
-        if ds[k] < 1e-14:
-            continue
-        cs = dataclasses.replace(ch, a=ch.a - y[k], b=ch.b + y[k])
-        u, _ = an.velocity(cs, x, np.full_like(x, -y[k]))
-        tot += ds[k] * u
-    return tot
-
-
 @pytest.mark.parametrize("kind", ["nf", "srf"])
 def test_thermocapillary_channel_vs_section_2(kind):
     # 64 x 32 channel, a = b = 16: NF (sigma_TT = 0) and SRF (sigma_T = 0).
@@ -190,7 +163,7 @@ def test_thermocapillary_channel_vs_section_2(kind):
     # magnitude: within 8% of the diffuse-interface superposition of the
     # sharp solution (the rest is the lattice's O(dx / b) response to a
     # stress concentrated on a few rows), and well below the sharp value
-    pred = diffuse_interface_prediction(c, c["W"])
+    pred = an.diffuse_interface_velocity(c)
     sharp = an.interface_velocity(ch, x)
     ratio = np.max(np.abs(ui)) / np.max(np.abs(pred))
     assert 0.92 < ratio <= 1.0
