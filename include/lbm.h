@@ -135,6 +135,13 @@ int lbm_profile_steps(lbm_ctx* ctx, int64_t n, double* ms);
  * the default.  LBM_EINVAL for any other shape. */
 int lbm_set_tile(lbm_ctx* ctx, int32_t tx, int32_t ty);
 
+/* Autotuner: time `reps` launches of the fused step kernel for every
+ * compiled tile shape on this context's channels and keep the fastest.  The
+ * state is not advanced (each launch gathers from the current buffer and
+ * writes the other one).  Outputs (may be NULL): chosen shape and its time
+ * per launch in ms.  Synchronises. */
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tx, int32_t* ty, double* ms);
+
 /* Number of lattice nodes over all instances, and device bytes held. */
 int lbm_info(lbm_ctx* ctx, int64_t* nodes, int64_t* device_bytes);
 

@@ -42,7 +42,8 @@ struct lbm_ctx {
     void* popB = nullptr;
     void* phi0 = nullptr;              // storage reference phi0 by row (float32 mode)
     void* phir = nullptr;              // zeroth moment of the streamed reference populations minus phi0, by row
-    void* r01 = nullptr;               // their y-moment by row
+    void* fq = nullptr;                // flux reference of f (half its y-moment) by row
+    void* fr = nullptr;                // constant part of the stored post-collision y-moment of f by row
     void* twall = nullptr;             // bottom-wall temperature by column
     float* tref = nullptr;             // per-node temperature reference (float32 mode)
     float* tref_new = nullptr;         // references written by a check step
@@ -196,7 +197,8 @@ void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
     a.phi0_v = c->phi0;
     a.tw_v = c->twall;
     a.phir_v = c->phir;
-    a.r01_v = c->r01;
+    a.fq_v = c->fq;
+    a.fr_v = c->fr;
     a.tref_v = c->tref;
     a.tref_out = c->tref_new;
     for (int k = 0; k < 4; ++k) a.snap[k] = c->snap + (size_t)k * c->total_nodes;
@@ -376,7 +378,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->popB = dev_alloc(c, (size_t)pop * c->elem);
     c->phi0 = dev_alloc(c, (size_t)rows * c->elem);
     c->phir = dev_alloc(c, (size_t)rows * c->elem);
-    c->r01 = dev_alloc(c, (size_t)rows * c->elem);
+    c->fq = dev_alloc(c, (size_t)rows * c->elem);
+    c->fr = dev_alloc(c, (size_t)rows * c->elem);
     c->twall = dev_alloc(c, (size_t)cols * c->elem);
     if (precision == LBM_FP32_DEV) {
         c->tref = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
@@ -391,7 +394,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->d_counter = (long long*)dev_alloc(c, sizeof(long long));
     c->d_tol = (double*)dev_alloc(c, sizeof(double));
     c->d_active = (int*)dev_alloc(c, sizeof(int));
-    if (!c->popA || !c->popB || !c->phi0 || !c->phir || !c->r01 || !c->twall || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
+    if (!c->popA || !c->popB || !c->phi0 || !c->phir || !c->fq || !c->fr || !c->twall || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
         !c->d_res || !c->d_counter || !c->d_tol || !c->d_active) {
         rc = LBM_ENOMEM;
     }
@@ -401,51 +404,72 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         // reference rows (float32 mode), rows -2 .. ny+1.  phi0: cold-start
         // tanh profile, the storage reference (float values).  A node pulls
         // populations stored relative to w_a phi0(source row) (the source row
-        // of a wall link is the node's own row); dR and r01 are the zeroth
-        // and y-moment of those references, dR taken relative to phi0(row).
-        // dR is rounded to float and then corrected by single ulps until the
-        // float values sum to zero exactly, as the exact values do: the
-        // float32 step then conserves sum phi up to the rounding of small
-        // deviations.
-        std::vector<double> t0(rows, 0.0), tr(rows, 0.0), t1(rows, 0.0);
+        // of a wall link is the node's own row); dR is the zeroth moment of
+        // those references taken relative to phi0(row).  dR is rounded to
+        // float and then corrected by single ulps until the float values sum
+        // to zero exactly, as the exact values do: the float32 step then
+        // conserves sum phi up to the rounding of small deviations.
+        //
+        // Flux reference of f.  At the interface the post-collision first
+        // moment of f (relaxed towards M theta n) is ~1e-2, far above the
+        // deviations of a near-steady state, and rounding it in float32 would
+        // put noise of its ulp into phi every step.  f is therefore also
+        // stored relative to q_a: +A(row)/2 on (0,+1), -A(row)/2 on (0,-1),
+        // whose raw moments are zero except m01 = A.  A is the fixed point of
+        // the ACE first-moment relaxation of the flat reference profile at
+        // rest (phi = phi0, u = 0, pull streaming, specular walls):
+        //   A(j) = (1 - w) [r01(j) + (A(j-1) + A(j+1)) / 2] + w M theta0 n0y,
+        // with r01 the pulled y-moment of w_a phi0 and A(-1) = -A(0),
+        // A(ny) = -A(ny-1) (the wall image of q), solved as a tridiagonal
+        // system.  fq = A/2 (float).  fr is what the stored post-collision
+        // y-moment keeps of the references after that subtraction,
+        //   fr(j) = (1 - w)(r01 + fq(j-1) + fq(j+1)) + w M theta0 n0y - 2 fq(j),
+        // with theta0, n0y of the reference profile as the step kernel forms
+        // them, so the kernel relaxes only deviations (tiny near steady
+        // state).  Any A is exact up to rounding; this one makes the stored
+        // values small.
+        std::vector<double> t0(rows, 0.0), tr(rows, 0.0), tq(rows, 0.0), tf(rows, 0.0);
         if (precision == LBM_FP32_DEV) {
             const int EYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
             const double Wh[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
             for (int k = 0; k < n_inst; ++k) {
                 const lbm_params& p = params[k];
+                const int ny = p.ny;
                 double* q0 = &t0[c->h_inst[k].row_off + 2];
                 double* qr = &tr[c->h_inst[k].row_off + 2];
-                double* q1 = &t1[c->h_inst[k].row_off + 2];
-                for (int j = -2; j <= p.ny + 1; ++j)
+                double* qq = &tq[c->h_inst[k].row_off + 2];
+                double* qf = &tf[c->h_inst[k].row_off + 2];
+                for (int j = -2; j <= ny + 1; ++j)
                     q0[j] = (double)(float)(0.5 * (1.0 + std::tanh(2.0 * ((p.b - 0.5) - (double)j) / p.W)));
-                for (int j = 0; j < p.ny; ++j) {
+                std::vector<double> r01(ny);
+                for (int j = 0; j < ny; ++j) {
                     double s0 = 0.0, s1 = 0.0;
                     for (int a2 = 0; a2 < 9; ++a2) {
                         int js = j - EYh[a2];
-                        if (js < 0 || js >= p.ny) js = j;
+                        if (js < 0 || js >= ny) js = j;
                         s0 += Wh[a2] * (q0[js] - q0[j]);
                         s1 += Wh[a2] * EYh[a2] * q0[js];
                     }
                     qr[j] = (double)(float)s0;
-                    q1[j] = s1;
+                    r01[j] = s1;
                 }
                 // exact-sum correction of the rounded dR (compensated sum)
                 auto fsum = [&]() {
                     double s = 0.0, comp = 0.0;
-                    for (int j = 0; j < p.ny; ++j) {
+                    for (int j = 0; j < ny; ++j) {
                         double y = qr[j] - comp, t = s + y;
                         comp = (t - s) - y;
                         s = t;
                     }
                     return s;
                 };
-                for (int it = 0; it < 4 * p.ny; ++it) {
+                for (int it = 0; it < 4 * ny; ++it) {
                     const double S = fsum();
                     if (S == 0.0) break;
                     // adjust the row whose float step best matches the residual
                     int best = -1;
                     double bestv = 0.0, bestr = std::fabs(S);
-                    for (int j = 0; j < p.ny; ++j) {
+                    for (int j = 0; j < ny; ++j) {
                         const float o = (float)qr[j];
                         const float nv = S > 0 ? std::nextafter(o, -INFINITY) : std::nextafter(o, INFINITY);
                         const double r = std::fabs(S + ((double)nv - (double)o));
@@ -454,6 +478,41 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
                     if (best < 0) break;
                     qr[best] = bestv;
                 }
+                // flux reference: tridiagonal solve (Thomas), rows 0 .. ny-1
+                const double w = 1.0 / (3.0 * p.M_phi + 0.5), cc = 0.5 * (1.0 - w);
+                const double eps2 = EPS_N * EPS_N;
+                auto mth = [&](double ph, double gy) {   // M theta n_y of a flat profile
+                    return p.M_phi * 4.0 * ph * (1.0 - ph) / p.W * (gy / std::sqrt(gy * gy + eps2));
+                };
+                std::vector<double> lo(ny), di(ny), up(ny), rhs(ny), A(ny);
+                for (int j = 0; j < ny; ++j) {
+                    // the physical profile: phi mirrored about the walls
+                    const double pm = j > 0 ? q0[j - 1] : q0[0], pp = j < ny - 1 ? q0[j + 1] : q0[ny - 1];
+                    rhs[j] = (1.0 - w) * r01[j] + w * mth(q0[j], 0.5 * (pp - pm));
+                    lo[j] = -cc;
+                    up[j] = -cc;
+                    di[j] = 1.0;
+                }
+                di[0] += cc;            // A(-1) = -A(0)
+                di[ny - 1] += cc;       // A(ny) = -A(ny-1)
+                if (ny == 1) di[0] = 1.0 + 2.0 * cc;
+                for (int j = 1; j < ny; ++j) {
+                    const double m = lo[j] / di[j - 1];
+                    di[j] -= m * up[j - 1];
+                    rhs[j] -= m * rhs[j - 1];
+                }
+                A[ny - 1] = rhs[ny - 1] / di[ny - 1];
+                for (int j = ny - 2; j >= 0; --j) A[j] = (rhs[j] - up[j] * A[j + 1]) / di[j];
+                for (int j = 0; j < ny; ++j) qq[j] = (double)(float)(0.5 * A[j]);
+                qq[-1] = -qq[0];
+                qq[ny] = -qq[ny - 1];
+                for (int j = 0; j < ny; ++j) {
+                    // reference theta0, n0y as the step kernel forms them
+                    // (tanh continuation into the ghost rows)
+                    const double fq_sum = qq[j - 1] + qq[j + 1];
+                    const double rest = mth(q0[j], 0.5 * (q0[j + 1] - q0[j - 1]));
+                    qf[j] = (double)(float)((1.0 - w) * (r01[j] + fq_sum) + w * rest - 2.0 * qq[j]);
+                }
             }
         }
         auto upload = [&](void* dst, const std::vector<double>& v) -> hipError_t {
@@ -461,7 +520,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
             std::vector<float> f(v.begin(), v.end());
             return hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
         };
-        if (upload(c->phi0, t0) != hipSuccess || upload(c->phir, tr) != hipSuccess || upload(c->r01, t1) != hipSuccess)
+        if (upload(c->phi0, t0) != hipSuccess || upload(c->phir, tr) != hipSuccess || upload(c->fq, tq) != hipSuccess ||
+            upload(c->fr, tf) != hipSuccess)
             rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
     }
     if (rc == LBM_OK) {
@@ -546,6 +606,7 @@ int lbm_init(lbm_ctx* c, const double* fields) {
     a.insts = c->d_inst;
     a.dst_v = c->popA;
     a.phi0_v = c->phi0;
+    a.fq_v = c->fq;
     a.tw_v = c->twall;
     a.tref = c->tref;
     a.cold = fields ? 0 : 1;
@@ -721,6 +782,7 @@ static int state_io(lbm_ctx* c, int32_t inst, double* host, int dir) {
     a.dir = dir;
     a.buf_v = (s & 1) ? c->popB : c->popA;
     a.phi0_v = c->phi0;
+    a.fq_v = c->fq;
     a.tw_v = c->twall;
     a.tref = c->tref;
     a.state = d;
@@ -774,6 +836,53 @@ int lbm_profile_steps(lbm_ctx* c, int64_t n, double* ms) {
     // index of the next check so that later checks report their own step
     long long next = ((c->steps + CHECK_EVERY - 1) / CHECK_EVERY) * CHECK_EVERY;
     HIPCHK(c, hipMemcpy(c->d_counter, &next, sizeof(long long), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tx_out, int32_t* ty_out, double* ms_out) {
+    if (!c || reps <= 0) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int best = -1;
+    double best_ms = 0.0;
+    const int tx0 = c->tx, ty0 = c->ty;
+    int rc = LBM_OK;
+    for (int s = 0; s < N_TILE_SHAPES && rc == LBM_OK; ++s) {
+        rc = lbm_set_tile(c, TILE_SHAPES[s][0], TILE_SHAPES[s][1]);
+        if (rc) break;
+        // the state buffer is only read: every launch gathers from it and
+        // writes the other buffer, which the next real step overwrites
+        StepArgs a;
+        step_args(c, a, (c->steps & 1) != 0);
+        for (int w = 0; w < 2 + reps && rc == LBM_OK; ++w) {
+            if (w == 2) {
+                if (hipEventRecord(e0, c->stream) != hipSuccess) rc = fail_hip(c, hipErrorUnknown, "event");
+            }
+            hipError_t e = launch_step(c->prec, a, 0, grid_of(c->n_tiles), c->tx, c->ty, c->stream);
+            if (e != hipSuccess) rc = fail_hip(c, e, "step kernel launch");
+        }
+        if (rc) break;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+        const double ms = (double)t / reps;
+        if (best < 0 || ms < best_ms) { best = s; best_ms = ms; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        (void)lbm_set_tile(c, tx0, ty0);
+        return rc;
+    }
+    rc = lbm_set_tile(c, TILE_SHAPES[best][0], TILE_SHAPES[best][1]);
+    if (rc) return rc;
+    if (tx_out) *tx_out = TILE_SHAPES[best][0];
+    if (ty_out) *ty_out = TILE_SHAPES[best][1];
+    if (ms_out) *ms_out = best_ms;
     return LBM_OK;
 }
 

@@ -50,7 +50,8 @@ struct StepArgs {
     const void* phi0_v;           // reference rows (compute type)
     const void* tw_v;             // bottom-wall temperature by column (compute type)
     const void* phir_v;           // zeroth moment of the streamed reference populations minus phi0, by row
-    const void* r01_v;            // their y-moment, by row
+    const void* fq_v;             // flux reference: half the reference y-moment of f, by row
+    const void* fr_v;             // constant part of the stored post-collision y-moment of f, by row
     const void* tref_v;           // per-node temperature reference (float32 mode)
     void* tref_out;               // new references written by a check step
     double* snap[4];              // ux, uy, T, phi at the last check
@@ -71,6 +72,7 @@ struct InitArgs {
     const Inst* insts;
     void* dst_v;
     const void* phi0_v;
+    const void* fq_v;
     const void* tw_v;
     float* tref;
     const double* fields[4];      // phi, ux, uy, T (device), when not cold
@@ -83,6 +85,7 @@ struct StateArgs {
     int dir;                      // 0: buffer -> state, 1: state -> buffer
     void* buf_v;
     const void* phi0_v;
+    const void* fq_v;
     const void* tw_v;
     const float* tref;
     double* state;                // device [3][9][ny][nx] float64

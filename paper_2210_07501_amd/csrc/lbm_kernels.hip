@@ -261,7 +261,8 @@ void step_kernel(StepArgs a) {
     __shared__ R s_dny[LY1 * LX1];  // n_y - n0_y
     __shared__ R s_phi0[LY2];       // storage reference phi0 of rows y0-2 .. y0+TY+1
     __shared__ R s_dR[LY2];         // phi of the streamed reference populations minus phi0, same rows
-    __shared__ R s_r01[LY2];        // their y-moment
+    __shared__ R s_fq[LY2 + 2];     // flux reference of f (A/2), rows y0-3 .. y0+TY+2
+    __shared__ R s_fr[LY2];         // constant part of the stored post-collision y-moment of f
     __shared__ R s_n0y[LY1];        // reference normal of rows y0-1 .. y0+TY
     __shared__ double s_red[(NT / 64) * 8];
 
@@ -307,7 +308,11 @@ void step_kernel(StepArgs a) {
         const int r = I.row_off + min(max(y0 - 2 + k, -2), ny + 1) + 2;
         s_phi0[k] = DEV ? ((const R*)a.phi0_v)[r] : R(0);
         s_dR[k] = DEV ? ((const R*)a.phir_v)[r] : R(0);
-        s_r01[k] = DEV ? ((const R*)a.r01_v)[r] : R(0);
+        s_fr[k] = DEV ? ((const R*)a.fr_v)[r] : R(0);
+    }
+    for (int k = tid; k < LY2 + 2; k += NT) {
+        const int r = I.row_off + min(max(y0 - 3 + k, -2), ny + 1) + 2;
+        s_fq[k] = DEV ? ((const R*)a.fq_v)[r] : R(0);
     }
     if (DEV) {
         const R* __restrict__ tref = (const R*)a.tref_v + I.node_off;
@@ -360,10 +365,11 @@ void step_kernel(StepArgs a) {
             rh[0] += c0;
             rh[3] += cx;
             rh[1] += cy;
-            rf[1] += s_r01[ty + 2];
             // phi - phi0(row), summed in float64 so that the step conserves
-            // sum phi up to the rounding of one small stored value
-            dph_d = (double)s_dR[ty + 2];
+            // sum phi up to the rounding of one small stored value.  rf[1]
+            // stays the y-moment of the stored deviations alone: the
+            // references' share of it is folded into the fr table.
+            dph_d = (double)s_dR[ty + 2] + ((double)s_fq[ty + 2] - (double)s_fq[ty + 4]);
 #pragma unroll
             for (int q = 0; q < 9; ++q) dph_d += (double)f[q];
             rf[0] = (R)dph_d;
@@ -392,7 +398,7 @@ void step_kernel(StepArgs a) {
                 R c0, cx, cy;
                 tcorr(hx, hy, jj, c0, cx, cy);
                 s3 += c0;
-                s1 += s_dR[hy + 2];
+                s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]);
             }
             s_phb[(hy + 2) * LX2 + hx + 2] = s1;
             s_pb[(hy + 1) * LX1 + hx + 1] = s2;
@@ -402,7 +408,7 @@ void step_kernel(StepArgs a) {
             R s1 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) s1 += tf[q];
-            if (DEV) s1 += s_dR[hy + 2];
+            if (DEV) s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]);
             s_phb[(hy + 2) * LX2 + hx + 2] = s1;
         }
     }
@@ -570,9 +576,12 @@ void step_kernel(StepArgs a) {
                 }
                 if (DEV) {
                     // move this node's temperature reference to its current
-                    // temperature: the values written below are stored
-                    // relative to it (the next steps read the new references)
-                    const R Tn = Tro + Tb;
+                    // temperature when it has drifted by more than 1e-6: the
+                    // values written below are stored relative to it (the
+                    // next steps read the new references).  Near steady state
+                    // the references stay put, so the float32 iteration can
+                    // settle instead of being re-rounded at every check.
+                    const R Tn = (Tb > R(1e-6) || Tb < R(-1e-6)) ? Tro + Tb : Tro;
                     Tb = Tb - (Tn - Tro);
                     Tr = Tn;
                     if (own_ok) ((R*)a.tref_out)[(size_t)I.node_off + (size_t)gj * nx + gi] = Tn;
@@ -585,14 +594,28 @@ void step_kernel(StepArgs a) {
             const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
 
             // --- ACE (Sec. 4.1): relax first central moments to M theta n ---
-            // stored as f - w phi0(row of this node)
+            // stored as f - w phi0(row of this node) - q (flux reference,
+            // float32 mode)
             {
                 const R ph0 = s_phi0[ty + 2];
                 const R dph = phb;                                // phi - phi0
+                const R k10 = rf[3] - ux * phi;
                 const R theta = R(4) * phi * (R(1) - phi) * p.inv_W;
-                const R k10 = rf[3] - ux * phi, k01 = rf[1] - uy * phi;
+                R t01;
+                if (DEV) {
+                    // deviation form: with k01 = kref + dk (kref the pulled
+                    // references' share) and theta n = theta0 n0y + d,
+                    //   t01 - A = (1 - w) dk + w M d + fr(row)
+                    const R dk01 = rf[1] - uy * phi;
+                    const R th0 = R(4) * ph0 * (R(1) - ph0) * p.inv_W;
+                    const R dth = R(4) * dph * (R(1) - phi - ph0) * p.inv_W;   // theta - theta0
+                    const R dtn = dth * nyv + th0 * s_dny[c1];                  // theta n_y - theta0 n0y
+                    t01 = dk01 + p.w_phi * (p.M * dtn - dk01) + s_fr[ty + 2];
+                } else {
+                    const R k01 = rf[1] - uy * phi;
+                    t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
+                }
                 const R t10 = k10 + p.w_phi * (p.M * theta * nxv - k10);
-                const R t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
                 // post-collision central moments minus ph0 * (rest central moments)
                 R c[9];
                 c[0] = dph;                                  // 00
@@ -604,6 +627,15 @@ void step_kernel(StepArgs a) {
                 c[6] = dph * cs2 - ph0 * ux2;                // 20
                 c[7] = ph0 * uy * (cs2 + ux2);               // 21
                 c[8] = dph * (cs2 * cs2) - ph0 * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
+                if (DEV) {
+                    // minus the other central moments of q (raw: m01 = A only)
+                    const R A = R(2) * s_fq[ty + 3];
+                    c[2] += R(2) * A * uy;
+                    c[4] += A * ux;
+                    c[5] -= R(2) * A * uxy;
+                    c[7] -= A * ux2;
+                    c[8] += R(2) * A * ux2 * uy;
+                }
                 central_to_raw(c, ux, uy);
                 raw_to_dist(c, f);
                 if (DEV) {
@@ -776,8 +808,9 @@ __global__ void count_active_kernel(const Inst* insts, int n, int* out) {
 
 // ---------------------------------------------------------------------------
 // Storage convention (float32 mode).  The value a node writes for direction
-// k is stored relative to that writer's own references: w_k phi0(row), w_k
-// p_r, w_k Tr(writer).  The node that pulls it (the neighbour at +e_k, or
+// k is stored relative to that writer's own references: w_k phi0(row) + q_k
+// (the flux reference, +-fq(row) on the two vertical directions), w_k p_r,
+// w_k Tr(writer).  The node that pulls it (the neighbour at +e_k, or
 // the writer itself through a wall link) adds them back.  In float64 mode all
 // references are zero.
 
@@ -843,6 +876,9 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     central_to_raw(cg, ux, uy); raw_to_dist(cg, eg);
     central_to_raw(ch, ux, uy); raw_to_dist(ch, eh);
     const R* phi0 = (const R*)a.phi0_v + I.row_off + 2;
+    const R* fq = (const R*)a.fq_v + I.row_off + 2;
+    // flux reference of direction k written at row r (float32 mode)
+    auto qf = [&](int kk, int r) { return (DEV && EX(kk) == 0 && EY(kk) != 0) ? EY(kk) * (double)fq[r] : 0.0; };
     const double pr = DEV ? I.p_r : 0.0;
     if (DEV) a.tref[I.node_off + q] = (float)T;
     const double Tr_self = DEV ? (double)(float)T : 0.0;
@@ -857,14 +893,14 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         if (js >= 0 && js < ny) {
             const double ph_w = DEV ? (double)phi0[js] : 0.0;
             const double T_w = DEV ? (double)(float)init_T_src(a, I, is, js, twr) : 0.0;
-            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k] - w * ph_w);
+            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k] - w * ph_w - qf(k, js));
             dst[pidx(nx, ny, 1, k, js, is)] = S(eg[k] - w * pr);
             dst[pidx(nx, ny, 2, k, js, is)] = S(eh[k] - w * T_w);
         } else {
             const int mir = MIRY(k), opp = OPP(k);
             const double Tw = (ey > 0) ? tw_at(i) : I.T_c;
             const double ph_w = DEV ? (double)phi0[j] : 0.0;
-            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k] - w * ph_w);
+            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k] - w * ph_w - qf(mir, j));
             dst[pidx(nx, ny, 1, opp, j, i)] = S(eg[k] - w * pr);
             // anti-bounce-back: h_k = -(stored + w Tr_self) + 2 w T_w
             dst[pidx(nx, ny, 2, opp, j, i)] = S(2.0 * w * Tw - w * Tr_self - eh[k]);
@@ -883,6 +919,8 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
     if (q >= n) return;
     const int i = (int)(q % nx), j = (int)(q / nx);
     const S* phi0 = (const S*)a.phi0_v + I.row_off + 2;
+    const S* fq = (const S*)a.fq_v + I.row_off + 2;
+    auto qf = [&](int kk, int r) { return (DEV && EX(kk) == 0 && EY(kk) != 0) ? EY(kk) * (double)fq[r] : 0.0; };
     const S* tw = (const S*)a.tw_v + I.col_off;
     const float* tref = a.tref ? a.tref + I.node_off : nullptr;
     const double pr = DEV ? I.p_r : 0.0;
@@ -897,13 +935,13 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
         double ref_f, ref_h, sgn_h = 1.0, add_h = 0.0;
         if (js >= 0 && js < ny) {
             kf = pidx(nx, ny, 0, k, js, is); kg = pidx(nx, ny, 1, k, js, is); kh = pidx(nx, ny, 2, k, js, is);
-            ref_f = DEV ? w * (double)phi0[js] : 0.0;
+            ref_f = DEV ? w * (double)phi0[js] + qf(k, js) : 0.0;
             ref_h = DEV ? w * (double)tref[(size_t)js * nx + is] : 0.0;
         } else {
             const int mir = MIRY(k), opp = OPP(k);
             const double Tw = (ey > 0) ? (double)tw[i] : I.T_c;
             kf = pidx(nx, ny, 0, mir, j, is); kg = pidx(nx, ny, 1, opp, j, i); kh = pidx(nx, ny, 2, opp, j, i);
-            ref_f = DEV ? w * (double)phi0[j] : 0.0;
+            ref_f = DEV ? w * (double)phi0[j] + qf(mir, j) : 0.0;
             // h_k = -(stored + w Tr_self) + 2 w T_w
             sgn_h = -1.0;
             ref_h = 0.0;

@@ -21,7 +21,7 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 
 # Every function declared in include/lbm.h.
 EXPORTS = ("lbm_create", "lbm_init", "lbm_step", "lbm_solve", "lbm_fields", "lbm_residual",
-           "lbm_get_state", "lbm_set_state", "lbm_profile_steps", "lbm_set_tile", "lbm_info",
+           "lbm_get_state", "lbm_set_state", "lbm_profile_steps", "lbm_set_tile", "lbm_autotune", "lbm_info",
            "lbm_destroy", "lbm_strerror")
 
 
@@ -68,6 +68,8 @@ def load():
     L.lbm_set_state.argtypes = [vp, ctypes.c_int32, dp]
     L.lbm_profile_steps.argtypes = [vp, ctypes.c_int64, dp]
     L.lbm_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.lbm_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               dp]
     L.lbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
@@ -245,6 +247,14 @@ def lbm_profile_steps(ctx: _Ctx, n: int) -> float:
 
 def lbm_set_tile(ctx: _Ctx, tx: int, ty: int):
     _check(load().lbm_set_tile(ctx.h, int(tx), int(ty)), "lbm_set_tile")
+
+
+def lbm_autotune(ctx: _Ctx, reps: int = 20):
+    """Pick the fastest compiled tile shape for this context; returns
+    ((tx, ty), ms per step launch)."""
+    tx, ty, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load().lbm_autotune(ctx.h, int(reps), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(ms)), "lbm_autotune")
+    return (tx.value, ty.value), ms.value
 
 
 def lbm_info(ctx: _Ctx):
