@@ -28,10 +28,11 @@ sys.path.insert(0, ROOT)
 METRIC = "coupled-LBM MLUPS & %HBM roofline; time-to-steady warm/batched vs cold FP64"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {0: 27 * 2 * 8, 1: 27 * 2 * 4}
-# HBM bytes per update measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE of the
-# step kernel, scaled by a plain copy kernel); None until measured for the
-# current kernel.
-MEASURED_TRAFFIC = {0: None, 1: None}
+# HBM bytes per update measured by rocprofv3 (FETCH_SIZE x 2.0 + WRITE_SIZE x
+# 1.0 of the every-step kernel, the factors read off a 1 GiB device copy),
+# tile 64x8; profiles/step_kernel_4096x2048_hbm_bytes.md.  Set to None when
+# the step kernel changes until it is measured again.
+MEASURED_TRAFFIC = {0: 501.9, 1: 240.4}
 
 
 def log(*a):
@@ -137,7 +138,7 @@ def main():
         traffic = MEASURED_TRAFFIC[prec]
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (traffic * r["nodes"]) if traffic else None,
+                "traffic": round(traffic * r["nodes"]) if traffic else None,
                 "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_update": bpu}
 
     if lbm.LBM_FP64 not in out or lbm.LBM_FP32_DEV not in out:
