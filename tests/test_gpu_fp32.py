@@ -6,7 +6,9 @@ Tolerances are the float32 error budget of this storage scheme, measured and
 stated per quantity (relative max-norm of each distribution; u on the scale
 of the peak interface velocity):
   populations f <= 1e-6, g <= 1e-8, h <= 1e-7 after 2000 steps;
-  u <= 5e-5 of the peak interface velocity after 2000 steps;
+  u <= 1e-5 of the peak interface velocity after 2000 steps of the small
+  channel (measured 8.0e-6; the step is deterministic, so the figure
+  reproduces exactly for a given build);
   sum phi drifts by < 1e-8 relative over 2000 steps."""
 import numpy as np
 import pytest
@@ -55,7 +57,7 @@ def test_small_channel_2000_steps_fp32(lbm):
     upk = np.nanmax(np.abs(an.interface_profile(R["ux"], R["phi"])))
     du = max(np.max(np.abs(F["ux"] - R["ux"])), np.max(np.abs(F["uy"] - R["uy"])))
     print("float32 errors: populations", errs, "u / peak interface u", du / upk, flush=True)
-    assert du <= 5e-5 * upk
+    assert du <= 1e-5 * upk
     assert rel_maxnorm(F["phi"], R["phi"]) <= 1e-6
     assert rel_maxnorm(F["T"], R["T"]) <= 1e-7
 

@@ -65,8 +65,8 @@ def test_analytic_channel_float64(lbm, kind):
 def test_analytic_channel_float32_vs_float64(lbm, kind):
     """The float32-deviation solve reaches the same steady state: peak
     interface velocity within 2% of the diffuse-interface solution, roll
-    count, and u within 5e-4 of the peak interface velocity of the float64
-    steady state (measured 4.5e-5 SRF, 1.4e-4 NF)."""
+    count, and u within 3e-4 of the peak interface velocity of the float64
+    steady state (measured 8.6e-5 SRF, 1.6e-4 NF)."""
     cfg = inputs.analytic_channel(kind)
     print("case: analytic channel", kind, "float32 vs float64", flush=True)
     F64, _ = solve(lbm, cfg, 0)
@@ -79,4 +79,4 @@ def test_analytic_channel_float32_vs_float64(lbm, kind):
     assert an.count_rolls(F32["uy"], cfg) == (8 if kind == "srf" else 4)
     du = max(np.max(np.abs(F32["ux"] - F64["ux"])), np.max(np.abs(F32["uy"] - F64["uy"])))
     print("float32 vs float64 steady u error / peak", du / peak, flush=True)
-    assert du <= 5e-4 * peak
+    assert du <= 3e-4 * peak
