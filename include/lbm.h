@@ -95,6 +95,14 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
  * and residual history. */
 int lbm_init(lbm_ctx* ctx, const double* fields);
 
+/* As lbm_init from given fields, but fields is device memory in the same
+ * layout (for each instance in order: phi, ux, uy, T, [ny][nx] each) -- the
+ * hand-off from a field predictor such as the warm-start network
+ * (nn_to_fields writes this layout).  The values are not checked on the
+ * host: a non-finite value shows up as LBM_EDIVERGED at the first check.
+ * LBM_EINVAL if fields is NULL. */
+int lbm_init_device(lbm_ctx* ctx, const double* fields);
+
 /* Advance every active instance by n >= 0 time steps (stream-ordered, no
  * synchronisation).  Every 100th step (counted from init) also records the
  * float64 residual, sum phi, sum rho and the peak interface velocity. */

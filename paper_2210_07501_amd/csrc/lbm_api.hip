@@ -589,7 +589,7 @@ int lbm_set_tile(lbm_ctx* c, int32_t tx, int32_t ty) {
     return upload_tables(c);
 }
 
-int lbm_init(lbm_ctx* c, const double* fields) {
+static int init_impl(lbm_ctx* c, const double* fields, bool device) {
     if (!c) return LBM_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     // reset descriptors (all active), results, counter
@@ -612,17 +612,19 @@ int lbm_init(lbm_ctx* c, const double* fields) {
     a.cold = fields ? 0 : 1;
     double* dfields = nullptr;
     if (fields) {
-        for (long long q = 0; q < 4 * c->total_nodes; ++q)
-            if (!std::isfinite(fields[q])) return LBM_EINVAL;
+        if (!device)
+            for (long long q = 0; q < 4 * c->total_nodes; ++q)
+                if (!std::isfinite(fields[q])) return LBM_EINVAL;
         dfields = (double*)dev_alloc(c, sizeof(double) * 4 * c->total_nodes);
         if (!dfields) return LBM_ENOMEM;
-        // host layout: per instance [phi|ux|uy|T]; device: field-major over all nodes
+        // input layout: per instance [phi|ux|uy|T]; kernel layout: field-major over all nodes
+        const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         for (int k = 0; k < c->n_inst; ++k) {
             const long long n = (long long)c->params[k].nx * c->params[k].ny;
             const double* src = fields + 4 * c->h_inst[k].node_off;
             for (int f = 0; f < 4; ++f)
                 HIPCHK(c, hipMemcpyAsync(dfields + f * c->total_nodes + c->h_inst[k].node_off, src + f * n,
-                                         sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+                                         sizeof(double) * n, kind, c->stream));
         }
         for (int f = 0; f < 4; ++f) a.fields[f] = dfields + f * c->total_nodes;
     } else {
@@ -635,6 +637,13 @@ int lbm_init(lbm_ctx* c, const double* fields) {
     c->steps = 0;
     c->initialised = true;
     return LBM_OK;
+}
+
+int lbm_init(lbm_ctx* c, const double* fields) { return init_impl(c, fields, false); }
+
+int lbm_init_device(lbm_ctx* c, const double* fields) {
+    if (!fields) return LBM_EINVAL;
+    return init_impl(c, fields, true);
 }
 
 int lbm_step(lbm_ctx* c, int64_t n) {

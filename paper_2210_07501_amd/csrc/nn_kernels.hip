@@ -1,0 +1,491 @@
+// Kernels of the warm-start network: 3x3 convolutions on BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) for the forward pass and
+// both backward passes, and the small elementwise / reduction kernels around
+// them (pooling, upsampling, skip add, ReLU backward, MSE loss, Adam).
+//
+// Tensors are NHWC, channels padded to a multiple of 32 and contiguous, in
+// bfloat16 (activations, their gradients, weight copies) or float32 (master
+// weights, weight gradients, optimiser moments, the network output).
+// Convolution geometry matches the channel domain: periodic in x (the
+// channel is periodic), zero padding in y (walls).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nn_internal.h"
+
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float b2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ __forceinline__ uint16_t f2b(float f) {
+    // round to nearest even (finite inputs)
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+    const uint4 v = *(const uint4*)p;
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+// ---------------------------------------------------------------------------
+// Convolution as an implicit GEMM: M = output pixels, N = output channels,
+// K = 9 taps x input channels.  One work-group = 4 waves = 64 consecutive
+// pixels of one image row; each wave owns 16 pixels and all NT x 16 output
+// channels.  Per K step of 32 channels a wave issues one A fragment load
+// (16 pixels x 32 channels of the tap's neighbour row, 16 bytes per lane)
+// and NT B fragment loads (weights [co][tap][ci], 16 bytes per lane).
+//
+// MFMA 16x16x32 operand layout: lane l supplies row (A) / column (B) l % 16
+// and K elements 8 (l / 16) .. 8 (l / 16) + 7; the result holds column l % 16,
+// rows 4 (l / 16) .. 4 (l / 16) + 3.
+template <int NT>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int segs = a.w >> 6;
+    const int seg = blockIdx.x % segs;
+    const int row = blockIdx.x / segs;           // n * h + y
+    const int y = row % a.h;
+    const int kq = lane >> 4, li = lane & 15;
+    const int px = (seg << 6) + (wave << 4) + li;   // this lane's A row pixel (x)
+    f32x4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int ci = a.ci;
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const int yy = y + dy;
+        const bool inb = yy >= 0 && yy < a.h;
+        int xx = px + dx;
+        xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
+        const uint16_t* xa = a.x + ((size_t)(inb ? row + dy : row) * a.w + xx) * ci + 8 * kq;
+        const uint16_t* wb = a.wt + ((size_t)li * 9 + t) * ci + 8 * kq;
+        for (int c0 = 0; c0 < ci; c0 += 32) {
+            const bf16x8 av = inb ? load8(xa + c0) : zero8();
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const bf16x8 bv = load8(wb + (size_t)j * 16 * 9 * ci + c0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: lane holds output channel 16 j + li for pixels 4 kq + r
+    const size_t pix0 = (size_t)row * a.w + (seg << 6) + (wave << 4) + 4 * kq;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = 16 * j + li;
+        const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float v = acc[j][r] + bias;
+            if (a.relu) v = v > 0.f ? v : 0.f;
+            const size_t p = pix0 + r;
+            if (a.y16) a.y16[p * a.co + co] = f2b(v);
+            if (a.y32 && co < a.y32_ch) a.y32[p * a.y32_ch + co] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient dW[co][t][ci] = sum_p dY[p][co] X[nbr(p, t)][ci] and bias
+// gradient, split over pixel chunks: block (chunk, tap) stages 64 pixels of
+// dY and of the tap-shifted X through LDS transposed to [channel][pixel], so
+// that MFMA fragments (8 consecutive pixels of one channel) are contiguous.
+// Partial sums go to work[chunk][co][9][ci] (and work_b[chunk][co]); a second
+// kernel adds the chunks in a fixed order.
+constexpr int WG_PIX = 64;                  // pixels per K step (two MFMA K=32)
+constexpr int LDS_PAD = 8;                  // row padding (bf16) against bank conflicts
+
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(WgradArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t s_dy[MAX_CH * (WG_PIX + LDS_PAD)];
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[MAX_CH * (WG_PIX + LDS_PAD)];
+    const int chunk = blockIdx.x, t = blockIdx.y;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, li = lane & 15;
+    const int co = a.co, ci = a.ci;
+    const int mt = co >> 4, ntl = ci >> 4, ntiles = mt * ntl;
+    constexpr int LS = WG_PIX + LDS_PAD;
+    // tiles of this wave: wave, wave + 4, ... (at most MAX_TILES_PER_WAVE)
+    f32x4 acc[MAX_TILES_PER_WAVE];
+#pragma unroll
+    for (int q = 0; q < MAX_TILES_PER_WAVE; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;   // bias partial of channel threadIdx.x (tap 4 blocks only)
+    const long long p_begin = (long long)chunk * a.chunk_pix;
+    const long long p_end = min(p_begin + a.chunk_pix, a.npix);
+    for (long long p0 = p_begin; p0 < p_end; p0 += WG_PIX) {
+        // stage: 64 pixels (one row segment, since w % 64 == 0 and chunks
+        // start on multiples of 64) of dY and of X at the tap's neighbours
+        const long long rowp = p0 / a.w;               // n * h + y
+        const int x0 = (int)(p0 - rowp * a.w);
+        const int y = (int)(rowp % a.h);
+        const int yy = y + dy;
+        const bool inb = yy >= 0 && yy < a.h;
+        for (int e = threadIdx.x; e < WG_PIX * co; e += 256) {
+            const int pp = e / co, c = e - pp * co;
+            s_dy[c * LS + pp] = a.dy[(size_t)(p0 + pp) * co + c];
+        }
+        for (int e = threadIdx.x; e < WG_PIX * ci; e += 256) {
+            const int pp = e / ci, c = e - pp * ci;
+            int xx = x0 + pp + dx;
+            xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
+            s_x[c * LS + pp] = inb ? a.x[((size_t)(rowp + dy) * a.w + xx) * ci + c] : (uint16_t)0;
+        }
+        __syncthreads();
+        if (a.db && t == 4 && (int)threadIdx.x < co) {
+            for (int pp = 0; pp < WG_PIX; ++pp) bsum += b2f(s_dy[threadIdx.x * LS + pp]);
+        }
+#pragma unroll
+        for (int q = 0; q < MAX_TILES_PER_WAVE; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < ntiles) {
+                const int mi = tile / ntl, nj = tile - mi * ntl;
+#pragma unroll
+                for (int h = 0; h < WG_PIX / 32; ++h) {
+                    const bf16x8 av = load8(&s_dy[(16 * mi + li) * LS + 32 * h + 8 * kq]);
+                    const bf16x8 bv = load8(&s_x[(16 * nj + li) * LS + 32 * h + 8 * kq]);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // partials: work[chunk][co][9][ci]
+    float* wp = a.work + (size_t)chunk * co * 9 * ci;
+#pragma unroll
+    for (int q = 0; q < MAX_TILES_PER_WAVE; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile < ntiles) {
+            const int mi = tile / ntl, nj = tile - mi * ntl;
+            const int cin = 16 * nj + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int cout = 16 * mi + 4 * kq + r;
+                wp[((size_t)cout * 9 + t) * ci + cin] = acc[q][r];
+            }
+        }
+    }
+    if (a.db && t == 4 && (int)threadIdx.x < co) a.work_b[(size_t)chunk * co + threadIdx.x] = bsum;
+}
+
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(WgradArgs a) {
+    const long long nw = (long long)a.co * 9 * a.ci;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k < nw) {
+        float s = 0.f;
+        for (int c = 0; c < a.n_chunks; ++c) s += a.work[(size_t)c * nw + k];
+        a.dw[k] = a.accumulate ? a.dw[k] + s : s;
+    } else if (a.db && k < nw + a.co) {
+        const int c0 = (int)(k - nw);
+        float s = 0.f;
+        for (int c = 0; c < a.n_chunks; ++c) s += a.work_b[(size_t)c * a.co + c0];
+        a.db[c0] = a.accumulate ? a.db[c0] + s : s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels (NHWC bf16).
+
+__global__ __launch_bounds__(256) void relu_bwd_kernel(const uint16_t* dy, const uint16_t* y, uint16_t* dx, long long n) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) dx[k] = b2f(y[k]) > 0.f ? dy[k] : (uint16_t)0;
+}
+
+__global__ __launch_bounds__(256) void add_kernel(const uint16_t* a, const uint16_t* b, uint16_t* o, long long n) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) o[k] = f2b(b2f(a[k]) + b2f(b[k]));
+}
+
+// 2x2 average pooling; (h, w) are the input sizes.
+__global__ __launch_bounds__(256) void pool_fwd_kernel(const uint16_t* x, uint16_t* y, int n, int h, int w, int c) {
+    const long long total = (long long)n * (h / 2) * (w / 2) * c;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const int ch = (int)(k % c);
+    long long q = k / c;
+    const int j = (int)(q % (w / 2));
+    q /= (w / 2);
+    const int i = (int)(q % (h / 2));
+    const int b = (int)(q / (h / 2));
+    const size_t base = (((size_t)b * h + 2 * i) * w + 2 * j) * c + ch;
+    const float s = b2f(x[base]) + b2f(x[base + c]) + b2f(x[base + (size_t)w * c]) + b2f(x[base + (size_t)w * c + c]);
+    y[k] = f2b(0.25f * s);
+}
+
+__global__ __launch_bounds__(256) void pool_bwd_kernel(const uint16_t* dy, uint16_t* dx, int n, int h, int w, int c) {
+    const long long total = (long long)n * h * w * c;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const int ch = (int)(k % c);
+    long long q = k / c;
+    const int xx = (int)(q % w);
+    q /= w;
+    const int yy = (int)(q % h);
+    const int b = (int)(q / h);
+    dx[k] = f2b(0.25f * b2f(dy[(((size_t)b * (h / 2) + yy / 2) * (w / 2) + xx / 2) * c + ch]));
+}
+
+// nearest-neighbour x2 upsampling; (h, w) are the input sizes.
+__global__ __launch_bounds__(256) void up_fwd_kernel(const uint16_t* x, uint16_t* y, int n, int h, int w, int c) {
+    const long long total = (long long)n * 4 * h * w * c;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const int ch = (int)(k % c);
+    long long q = k / c;
+    const int xx = (int)(q % (2 * w));
+    q /= (2 * w);
+    const int yy = (int)(q % (2 * h));
+    const int b = (int)(q / (2 * h));
+    y[k] = x[(((size_t)b * h + yy / 2) * w + xx / 2) * c + ch];
+}
+
+__global__ __launch_bounds__(256) void up_bwd_kernel(const uint16_t* dy, uint16_t* dx, int n, int h, int w, int c) {
+    const long long total = (long long)n * h * w * c;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const int ch = (int)(k % c);
+    long long q = k / c;
+    const int j = (int)(q % w);
+    q /= w;
+    const int i = (int)(q % h);
+    const int b = (int)(q / h);
+    const size_t base = (((size_t)b * 2 * h + 2 * i) * 2 * w + 2 * j) * c + ch;
+    const size_t rs = (size_t)2 * w * c;
+    dx[k] = f2b(b2f(dy[base]) + b2f(dy[base + c]) + b2f(dy[base + rs]) + b2f(dy[base + rs + c]));
+}
+
+// MSE over the nch real output channels: loss = sum (pred - tgt)^2 / (npix nch);
+// dpred (bf16, cpad channels, zero beyond nch) = 2 (pred - tgt) / (npix nch).
+// Per-block float64 partial sums of the loss go to partial[block].
+__global__ __launch_bounds__(256) void mse_kernel(const float* pred, const float* tgt, uint16_t* dpred, double* partial,
+                                                  long long npix, int nch, int cpad) {
+    __shared__ double s[256];
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    if (k < npix) {
+        const float inv = 1.0f / (float)((double)npix * nch);
+        for (int c = 0; c < nch; ++c) {
+            const float d = pred[k * nch + c] - tgt[k * nch + c];
+            l += (double)d * d;
+            if (dpred) dpred[k * cpad + c] = f2b(2.f * d * inv);
+        }
+        if (dpred)
+            for (int c = nch; c < cpad; ++c) dpred[k * cpad + c] = 0;
+    }
+    s[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void sum_kernel(const double* partial, int n, double scale, double* out) {
+    __shared__ double s[256];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) v += partial[k];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0] * scale;
+}
+
+// Adam (bias-corrected) on float32 master weights [co][9][ci]; refreshes the
+// bf16 copy and the flipped, transposed copy [ci][8 - t][co] that the
+// data-gradient convolution uses.  wflip may be null (bias vectors: co = n,
+// ci = 1, taps = 1).
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= a.n) return;
+    const float g = a.g[k];
+    const float m = a.b1 * a.m[k] + (1.f - a.b1) * g;
+    const float v = a.b2 * a.v[k] + (1.f - a.b2) * g * g;
+    a.m[k] = m;
+    a.v[k] = v;
+    const float mh = m * a.c1, vh = v * a.c2;
+    float w = a.w[k];
+    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * w);
+    a.w[k] = w;
+    const uint16_t wb = f2b(w);
+    if (a.w16) a.w16[k] = wb;
+    if (a.wflip) {
+        const int ci = (int)(k % a.ci);
+        const long long q = k / a.ci;
+        const int t = (int)(q % 9);
+        const int co = (int)(q / 9);
+        a.wflip[((size_t)ci * 9 + (8 - t)) * a.co + co] = wb;
+    }
+}
+
+// float32 master weights -> bf16 copy and flipped copy (set-up, no update)
+__global__ __launch_bounds__(256) void wcast_kernel(const float* w, uint16_t* w16, uint16_t* wflip, int co, int ci) {
+    const long long n = (long long)co * 9 * ci;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const uint16_t wb = f2b(w[k]);
+    w16[k] = wb;
+    if (wflip) {
+        const int c = (int)(k % ci);
+        const long long q = k / ci;
+        const int t = (int)(q % 9);
+        const int o = (int)(q / 9);
+        wflip[((size_t)c * 9 + (8 - t)) * co + o] = wb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Channel features and the hand-off to the LBM.
+
+__device__ __forceinline__ double phi_tanh(const ChanDesc& d, int j) {
+    return 0.5 * (1.0 + tanh(2.0 * ((d.b - 0.5) - (double)j) / d.W));
+}
+
+// x[n][y][x][cpad]: the 8 input planes of channel n (the rest zero).
+__global__ __launch_bounds__(256) void features_kernel(const ChanDesc* desc, uint16_t* x, int n, int h, int w, int cpad) {
+    const long long total = (long long)n * h * w;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const int i = (int)(k % w);
+    const int j = (int)((k / w) % h);
+    const int b = (int)(k / ((long long)w * h));
+    const ChanDesc& d = desc[b];
+    const double ph = phi_tanh(d, j);
+    float f[NFEAT];
+    f[0] = (float)(d.dT * cos(2.0 * 3.14159265358979323846 * (double)i / d.l) + (d.T_h - d.T_ref));
+    f[1] = (float)ph;
+    f[2] = (float)((d.mu_a + ph * (d.mu_b - d.mu_a)) / d.mu_b);
+    f[3] = (float)((d.k_a + ph * (d.k_b - d.k_a)) / d.k_b);
+    f[4] = (float)(d.sigma_T / 2e-4);
+    f[5] = (float)(d.sigma_TT / 3e-4);
+    f[6] = (float)(((double)j + 0.5) / h);
+    f[7] = (float)(d.b / h);
+    uint16_t* o = x + (size_t)k * cpad;
+    for (int c = 0; c < cpad; ++c) o[c] = c < NFEAT ? f2b(f[c]) : (uint16_t)0;
+}
+
+// pred[n][y][x][4] (u / U_s, v / U_s, (T - T_ref) / dT, phi) -> LBM init fields
+// [n][phi | ux | uy | T][y][x] in float64; phi clipped to [0, 1].
+__global__ __launch_bounds__(256) void to_fields_kernel(const ChanDesc* desc, const float* pred, double* fields, int n, int h, int w) {
+    const long long total = (long long)n * h * w;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const long long hw = (long long)h * w;
+    const int b = (int)(k / hw);
+    const long long q = k - b * hw;
+    const ChanDesc& d = desc[b];
+    const float* p = pred + (size_t)k * 4;
+    double ph = (double)p[3];
+    ph = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
+    double* o = fields + (size_t)b * 4 * hw;
+    o[q] = ph;
+    o[hw + q] = (double)p[0] * d.U_s;
+    o[2 * hw + q] = (double)p[1] * d.U_s;
+    o[3 * hw + q] = d.T_ref + d.dT * (double)p[2];
+}
+
+// converged LBM fields [n][phi | ux | uy | T][y][x] float64 -> targets [n][y][x][4] float32
+__global__ __launch_bounds__(256) void targets_kernel(const ChanDesc* desc, const double* fields, float* tgt, int n, int h, int w) {
+    const long long total = (long long)n * h * w;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    const long long hw = (long long)h * w;
+    const int b = (int)(k / hw);
+    const long long q = k - b * hw;
+    const ChanDesc& d = desc[b];
+    const double* f = fields + (size_t)b * 4 * hw;
+    float* o = tgt + (size_t)k * 4;
+    o[0] = (float)(f[hw + q] / d.U_s);
+    o[1] = (float)(f[2 * hw + q] / d.U_s);
+    o[2] = (float)((f[3 * hw + q] - d.T_ref) / d.dT);
+    o[3] = (float)f[q];
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
+    const unsigned grid = (unsigned)((long long)a.n * a.h * (a.w / 64));
+    switch (a.co / 16) {
+        case 2: conv_fwd_kernel<2><<<grid, 256, 0, st>>>(a); break;
+        case 4: conv_fwd_kernel<4><<<grid, 256, 0, st>>>(a); break;
+        case 6: conv_fwd_kernel<6><<<grid, 256, 0, st>>>(a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_wgrad(const WgradArgs& a, hipStream_t st) {
+    conv_wgrad_kernel<<<dim3((unsigned)a.n_chunks, 9), 256, 0, st>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    wgrad_reduce_kernel<<<blocks_of((long long)a.co * 9 * a.ci + a.co), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dx, long long n, hipStream_t st) {
+    relu_bwd_kernel<<<blocks_of(n), 256, 0, st>>>(dy, y, dx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const uint16_t* a, const uint16_t* b, uint16_t* o, long long n, hipStream_t st) {
+    add_kernel<<<blocks_of(n), 256, 0, st>>>(a, b, o, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool(int dir, const uint16_t* in, uint16_t* out, int n, int h, int w, int c, hipStream_t st) {
+    if (dir == 0) pool_fwd_kernel<<<blocks_of((long long)n * (h / 2) * (w / 2) * c), 256, 0, st>>>(in, out, n, h, w, c);
+    else pool_bwd_kernel<<<blocks_of((long long)n * h * w * c), 256, 0, st>>>(in, out, n, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_up(int dir, const uint16_t* in, uint16_t* out, int n, int h, int w, int c, hipStream_t st) {
+    if (dir == 0) up_fwd_kernel<<<blocks_of((long long)n * 4 * h * w * c), 256, 0, st>>>(in, out, n, h, w, c);
+    else up_bwd_kernel<<<blocks_of((long long)n * h * w * c), 256, 0, st>>>(in, out, n, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(const float* pred, const float* tgt, uint16_t* dpred, double* partial, double* out,
+                      long long npix, int nch, int cpad, hipStream_t st) {
+    const unsigned nb = blocks_of(npix);
+    mse_kernel<<<nb, 256, 0, st>>>(pred, tgt, dpred, partial, npix, nch, cpad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sum_kernel<<<1, 256, 0, st>>>(partial, (int)nb, 1.0 / ((double)npix * nch), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t st) {
+    adam_kernel<<<blocks_of(a.n), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_wcast(const float* w, uint16_t* w16, uint16_t* wflip, int co, int ci, hipStream_t st) {
+    wcast_kernel<<<blocks_of((long long)co * 9 * ci), 256, 0, st>>>(w, w16, wflip, co, ci);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const ChanDesc* d, uint16_t* x, int n, int h, int w, int cpad, hipStream_t st) {
+    features_kernel<<<blocks_of((long long)n * h * w), 256, 0, st>>>(d, x, n, h, w, cpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_fields(const ChanDesc* d, const float* pred, double* fields, int n, int h, int w, hipStream_t st) {
+    to_fields_kernel<<<blocks_of((long long)n * h * w), 256, 0, st>>>(d, pred, fields, n, h, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(const ChanDesc* d, const double* fields, float* tgt, int n, int h, int w, hipStream_t st) {
+    targets_kernel<<<blocks_of((long long)n * h * w), 256, 0, st>>>(d, fields, tgt, n, h, w);
+    return hipGetLastError();
+}
+
+}  // namespace nn

@@ -20,7 +20,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_ESTATE = 0, -1, 
 LBM_FP64, LBM_FP32_DEV = 0, 1
 
 # Every function declared in include/lbm.h.
-EXPORTS = ("lbm_create", "lbm_init", "lbm_step", "lbm_solve", "lbm_fields", "lbm_residual",
+EXPORTS = ("lbm_create", "lbm_init", "lbm_init_device", "lbm_step", "lbm_solve", "lbm_fields", "lbm_residual",
            "lbm_get_state", "lbm_set_state", "lbm_profile_steps", "lbm_set_tile", "lbm_autotune", "lbm_info",
            "lbm_destroy", "lbm_strerror")
 
@@ -60,6 +60,7 @@ def load():
     L.lbm_create.argtypes = [ctypes.POINTER(lbm_params), ctypes.c_int32, ctypes.c_int32, vp,
                              ALLOC_FN, FREE_FN, vp, ctypes.POINTER(vp)]
     L.lbm_init.argtypes = [vp, dp]
+    L.lbm_init_device.argtypes = [vp, vp]
     L.lbm_step.argtypes = [vp, ctypes.c_int64]
     L.lbm_solve.argtypes = [vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
     L.lbm_fields.argtypes = [vp, ctypes.c_int32, dp, dp, dp, dp, dp]
@@ -194,6 +195,16 @@ def lbm_init(ctx: _Ctx, fields=None):
             parts.append(np.ascontiguousarray(a, dtype=np.float64).reshape(ny * nx))
     buf = np.ascontiguousarray(np.concatenate(parts))
     _check(load().lbm_init(ctx.h, _dp(buf)), "lbm_init")
+
+
+def lbm_init_device(ctx: _Ctx, fields):
+    """fields: a float64 CUDA tensor (or device address) holding, for each
+    channel in order, phi, ux, uy, T ([ny][nx] each)."""
+    ptr = fields if isinstance(fields, int) else fields.data_ptr()
+    if not isinstance(fields, int):
+        need = sum(4 * nx * ny for ny, nx in (ctx.shape(k) for k in range(len(ctx.cfgs))))
+        assert fields.is_cuda and fields.dtype.itemsize == 8 and fields.is_contiguous() and fields.numel() == need
+    _check(load().lbm_init_device(ctx.h, ctypes.c_void_p(ptr)), "lbm_init_device")
 
 
 def lbm_step(ctx: _Ctx, n: int):

@@ -11,12 +11,13 @@ from paper_2210_07501_amd import inputs, lbm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
+NN_HEADER = os.path.join(ROOT, "include", "lbm_nn.h")
 
 
-def declared_functions():
-    txt = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="lbm_"):
+    txt = open(header).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt))
+    names = set(re.findall(r"\b(%s[a-z0-9_]+)\s*\(" % prefix, txt))
     # typedef'd function-pointer types are not exports
     names -= {"lbm_alloc_fn", "lbm_free_fn"}
     return names
@@ -27,6 +28,16 @@ def test_library_exports_every_declared_function():
     names = declared_functions()
     assert names, "no declarations parsed"
     assert names == set(lbm.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_library_exports_every_network_function():
+    from paper_2210_07501_amd import nn
+    L = nn.load()
+    names = declared_functions(NN_HEADER, "nn_")
+    assert names, "no declarations parsed"
+    assert names == set(nn.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
 
