@@ -54,6 +54,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblbm.so not built: run `python -m paper_2210_07501_amd.build` "
                            "(there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime.  Load it first so that the library
+    # binds to that same runtime (same soname): loaded the other way round,
+    # the process maps two runtimes and torch's device memory and streams are
+    # foreign to the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)
     vp = ctypes.c_void_p
@@ -122,13 +130,15 @@ class _TorchAllocator:
         self.torch = torch
         self.device = device
         self.live = {}
+        self.last_error = None
         self.alloc_cb = ALLOC_FN(self._alloc)
         self.free_cb = FREE_FN(self._free)
 
     def _alloc(self, nbytes, user):
         try:
             t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
-        except RuntimeError:
+        except Exception as e:          # reported by lbm_create (an exception must not cross the C frame)
+            self.last_error = "%s allocating %d bytes: %s" % (type(e).__name__, int(nbytes), e)
             return None
         ptr = t.data_ptr()
         self.live[ptr] = t
@@ -160,7 +170,10 @@ def lbm_create(cfgs, precision: int = LBM_FP64, stream=None, torch_alloc: bool =
     h = ctypes.c_void_p()
     a_cb = alloc.alloc_cb if alloc else ALLOC_FN()
     f_cb = alloc.free_cb if alloc else FREE_FN()
-    _check(L.lbm_create(arr, len(cfgs), int(precision), st, a_cb, f_cb, None, ctypes.byref(h)), "lbm_create")
+    rc = L.lbm_create(arr, len(cfgs), int(precision), st, a_cb, f_cb, None, ctypes.byref(h))
+    if rc != LBM_OK and alloc is not None and alloc.last_error:
+        raise LBMError(rc, "lbm_create (%s)" % alloc.last_error)
+    _check(rc, "lbm_create")
     return _Ctx(h, cfgs, alloc, precision)
 
 
