@@ -11,8 +11,10 @@ kernel.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS of the float64 path (value), the float32-deviation
 path alongside, the roofline of the dominant kernel (HBM-bound; algorithmic
-bytes 432 B per node update in float64, 216 B in float32), and the CPU
-oracle's rate on a bounded sample.
+bytes 432 B per node update in float64, 216 B in float32), the time to
+steady state of 16 held-out 256 x 128 channels (plain float64 channel by
+channel vs one warm-started float32 batch vs one cold float32 batch), and
+the CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -90,12 +92,60 @@ def cpu_baseline(target_s=15.0):
                 sample="256x128 sub-run of the throughput channel (1/16 scale), %d steps from rest, %.1f s" % (n, dt))
 
 
+def time_to_steady(n=16, cap=400_000):
+    """Time to residual 1e-8 on n held-out warm-start channels (256 x 128,
+    seeds 900000 + i): plain float64 solves from rest, one channel at a time,
+    against one batched float32-deviation solve started from the trained
+    network's prediction (inference included) and one from rest."""
+    import numpy as np
+    import torch
+
+    from paper_2210_07501_amd import inputs, lbm
+    from paper_2210_07501_amd import warmstart as ws
+
+    cfgs = inputs.warmstart_set(n, 900_000)
+    net = ws.WarmStartNet()
+    net.load_state(os.path.join(ROOT, "paper_2210_07501_amd", "weights", "warmstart.npz"))
+    net.predict_fields(cfgs[:2])          # first-call set-up outside the timing
+    t_single, st_single, r_single = 0.0, [], []
+    for c in cfgs:
+        ctx, wall, res = ws.solve_batch([c], lbm.LBM_FP64, cap=cap, verbose=False)
+        lbm.lbm_destroy(ctx)
+        t_single += wall
+        st_single.append(res[0]["steps"])
+        r_single.append(res[0])
+    log("bench: cold float64 single-channel solves %.1f s" % t_single)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = net.predict_fields(cfgs)
+    torch.cuda.synchronize()
+    t_nn = time.perf_counter() - t0
+    ctx, wall_w, res_w = ws.solve_batch(cfgs, lbm.LBM_FP32_DEV, cap=cap, init_fields=pred, verbose=False)
+    lbm.lbm_destroy(ctx)
+    ctx, wall_c, res_c = ws.solve_batch(cfgs, lbm.LBM_FP32_DEV, cap=cap, verbose=False)
+    lbm.lbm_destroy(ctx)
+    log("bench: warm batch %.1f s, cold batch %.1f s" % (wall_w + t_nn, wall_c))
+    conv = lambda res: int(sum(r["r"] <= 1e-8 for r in res))
+    med = lambda res: int(np.median([r["steps"] for r in res]))
+    return {"channels": n, "workload": "held-out warm-start channels 256x128 (seeds 900000+i)",
+            "cold_fp64_single_s": round(t_single, 2), 
+            "warm_fp32_batch_s": round(wall_w + t_nn, 2), "inference_s": round(t_nn, 3),
+            "cold_fp32_batch_s": round(wall_c, 2),
+            "ratio_cold_fp64_over_warm": round(t_single / (wall_w + t_nn), 2),
+            "ratio_cold_batch_over_warm": round(wall_c / (wall_w + t_nn), 2),
+            "median_steps": {"cold_fp64": int(np.median(st_single)), "warm_fp32": med(res_w), "cold_fp32": med(res_c)},
+            "converged": {"cold_fp64": conv(r_single), "warm_fp32": conv(res_w), "cold_fp32": conv(res_c)},
+            "cap": cap}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the time-to-steady comparison (16 held-out channels, about a minute)")
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both")
     ap.add_argument("--calib-copy", action="store_true",
@@ -164,6 +214,9 @@ def main():
         "fp32_dev": {"value": round(mlups32, 1), "unit": "MLUPS", "dtype": "f32",
                      "ms_per_step": round(r32["ms_total"] / args.steps, 4), "roofline": roof(lbm.LBM_FP32_DEV)},
     }
+    if not args.no_warmstart:
+        log("bench: time to steady state (warm-started batch vs cold float64 channel by channel)")
+        line["time_to_steady"] = time_to_steady()
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()

@@ -107,14 +107,21 @@ int nn_cast_weights(const float* w, uint16_t* w16, uint16_t* wflip, int32_t co, 
  *   2 mu(phi) / mu_b, 3 k(phi) / k_b,
  *   4 sigma_T / 2e-4, 5 sigma_TT / 3e-4,
  *   6 (y + 1/2) / ny, 7 b / ny,
- * zero beyond.  cpad >= 8.  Synchronises. */
+ *   8 ln(mu_a / mu_b) / ln 5, 9 ln(k_a / k_b) / ln 5 (both layers' properties
+ *     everywhere, not only inside each layer),
+ * zero beyond.  cpad >= 10.  Synchronises. */
 int nn_features(const lbm_params* params, int32_t n, uint16_t* x, int32_t cpad, void* stream);
 
 /* Network output pred [n][ny][nx][4] float32 (u / U_s, v / U_s,
  * (T - T_ref) / dT, phi) -> fields [n][phi | ux | uy | T][ny][nx] float64
- * in the layout lbm_init_device reads; phi is clipped to [0, 1].
+ * in the layout lbm_init_device reads.  phi_from_net != 0: phi is the
+ * network's output clipped to [0, 1]; 0: the cold-start tanh profile (the
+ * conservative Allen-Cahn equation removes a bulk error in phi only by
+ * diffusion at mobility M_phi, far slower than u and T relax, and it keeps
+ * sum phi, so the hand-off keeps the exact initial interface).
  * Synchronises. */
-int nn_to_fields(const lbm_params* params, int32_t n, const float* pred, double* fields, void* stream);
+int nn_to_fields(const lbm_params* params, int32_t n, const float* pred, double* fields, int32_t phi_from_net,
+                 void* stream);
 
 /* Inverse map: fields [n][phi | ux | uy | T][ny][nx] float64 -> training
  * targets [n][ny][nx][4] float32.  Synchronises. */

@@ -197,10 +197,11 @@ int nn_features(const lbm_params* params, int32_t n, uint16_t* x, int32_t cpad, 
     });
 }
 
-int nn_to_fields(const lbm_params* params, int32_t n, const float* pred, double* fields, void* stream) {
+int nn_to_fields(const lbm_params* params, int32_t n, const float* pred, double* fields, int32_t phi_from_net,
+                 void* stream) {
     if (!pred || !fields) return LBM_EINVAL;
     return with_desc(params, n, S(stream), [&](const ChanDesc* d) {
-        return launch_to_fields(d, pred, fields, n, params[0].ny, params[0].nx, S(stream));
+        return launch_to_fields(d, pred, fields, n, params[0].ny, params[0].nx, phi_from_net ? 1 : 0, S(stream));
     });
 }
 

@@ -8,7 +8,7 @@ namespace nn {
 
 constexpr int MAX_CH = 96;               // widest layer (channels, padded to 32)
 constexpr int MAX_TILES_PER_WAVE = 9;    // (96 / 16)^2 weight-gradient tiles over 4 waves
-constexpr int NFEAT = 8;                 // input planes
+constexpr int NFEAT = 10;                // input planes
 
 // Per-channel description for the feature and hand-off kernels.
 struct ChanDesc {
@@ -61,7 +61,8 @@ hipError_t launch_mse(const float* pred, const float* tgt, uint16_t* dpred, doub
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 hipError_t launch_wcast(const float* w, uint16_t* w16, uint16_t* wflip, int co, int ci, hipStream_t st);
 hipError_t launch_features(const ChanDesc* d, uint16_t* x, int n, int h, int w, int cpad, hipStream_t st);
-hipError_t launch_to_fields(const ChanDesc* d, const float* pred, double* fields, int n, int h, int w, hipStream_t st);
+hipError_t launch_to_fields(const ChanDesc* d, const float* pred, double* fields, int n, int h, int w, int phi_net,
+                            hipStream_t st);
 hipError_t launch_targets(const ChanDesc* d, const double* fields, float* tgt, int n, int h, int w, hipStream_t st);
 
 }  // namespace nn

@@ -35,11 +35,12 @@ __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, ma
 
 // ---------------------------------------------------------------------------
 // Convolution as an implicit GEMM: M = output pixels, N = output channels,
-// K = 9 taps x input channels.  One work-group = 4 waves = 64 consecutive
-// pixels of one image row; each wave owns 16 pixels and all NT x 16 output
-// channels.  Per K step of 32 channels a wave issues one A fragment load
-// (16 pixels x 32 channels of the tap's neighbour row, 16 bytes per lane)
-// and NT B fragment loads (weights [co][tap][ci], 16 bytes per lane).
+// K = 9 taps x input channels.  Each wave owns one 64-pixel row segment
+// (four 16-pixel M tiles) and all NT x 16 output channels; a work-group is
+// four consecutive segments.  Per K step of 32 channels a wave loads four A
+// fragments (16 pixels x 32 channels of the tap's neighbour row, 16 bytes per
+// lane) and NT B fragments (weights [co][tap][ci]); each B fragment feeds
+// four MFMAs.
 //
 // MFMA 16x16x32 operand layout: lane l supplies row (A) / column (B) l % 16
 // and K elements 8 (l / 16) .. 8 (l / 16) + 7; the result holds column l % 16,
@@ -48,45 +49,62 @@ template <int NT>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int segs = a.w >> 6;
-    const int seg = blockIdx.x % segs;
-    const int row = blockIdx.x / segs;           // n * h + y
+    const long long nseg = (long long)a.n * a.h * segs;
+    const long long sg = (long long)blockIdx.x * 4 + wave;
+    if (sg >= nseg) return;
+    const int seg = (int)(sg % segs);
+    const int row = (int)(sg / segs);            // n * h + y
     const int y = row % a.h;
     const int kq = lane >> 4, li = lane & 15;
-    const int px = (seg << 6) + (wave << 4) + li;   // this lane's A row pixel (x)
-    f32x4 acc[NT];
+    const int x0 = seg << 6;
+    f32x4 acc[4][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int ci = a.ci;
     for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
         const int yy = y + dy;
         const bool inb = yy >= 0 && yy < a.h;
-        int xx = px + dx;
-        xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
-        const uint16_t* xa = a.x + ((size_t)(inb ? row + dy : row) * a.w + xx) * ci + 8 * kq;
+        const size_t rbase = (size_t)(inb ? row + dy : row) * a.w;
+        const uint16_t* xa[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int xx = x0 + 16 * m + li + dx;
+            xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
+            xa[m] = a.x + (rbase + xx) * ci + 8 * kq;
+        }
         const uint16_t* wb = a.wt + ((size_t)li * 9 + t) * ci + 8 * kq;
         for (int c0 = 0; c0 < ci; c0 += 32) {
-            const bf16x8 av = inb ? load8(xa + c0) : zero8();
+            bf16x8 av[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) av[m] = inb ? load8(xa[m] + c0) : zero8();
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 const bf16x8 bv = load8(wb + (size_t)j * 16 * 9 * ci + c0);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m][j], 0, 0, 0);
             }
         }
     }
-    // epilogue: lane holds output channel 16 j + li for pixels 4 kq + r
-    const size_t pix0 = (size_t)row * a.w + (seg << 6) + (wave << 4) + 4 * kq;
+    // epilogue: lane holds output channel 16 j + li for pixels 16 m + 4 kq + r
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int co = 16 * j + li;
         const float bias = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float v = acc[j][r] + bias;
-            if (a.relu) v = v > 0.f ? v : 0.f;
-            const size_t p = pix0 + r;
-            if (a.y16) a.y16[p * a.co + co] = f2b(v);
-            if (a.y32 && co < a.y32_ch) a.y32[p * a.y32_ch + co] = v;
+        for (int m = 0; m < 4; ++m) {
+            const size_t pix0 = (size_t)row * a.w + x0 + 16 * m + 4 * kq;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v = acc[m][j][r] + bias;
+                if (a.relu) v = v > 0.f ? v : 0.f;
+                const size_t p = pix0 + r;
+                if (a.y16) a.y16[p * a.co + co] = f2b(v);
+                if (a.y32 && co < a.y32_ch) a.y32[p * a.y32_ch + co] = v;
+            }
         }
     }
 }
@@ -368,13 +386,17 @@ __global__ __launch_bounds__(256) void features_kernel(const ChanDesc* desc, uin
     f[5] = (float)(d.sigma_TT / 3e-4);
     f[6] = (float)(((double)j + 0.5) / h);
     f[7] = (float)(d.b / h);
+    f[8] = (float)(log(d.mu_a / d.mu_b) / log(5.0));
+    f[9] = (float)(log(d.k_a / d.k_b) / log(5.0));
     uint16_t* o = x + (size_t)k * cpad;
     for (int c = 0; c < cpad; ++c) o[c] = c < NFEAT ? f2b(f[c]) : (uint16_t)0;
 }
 
 // pred[n][y][x][4] (u / U_s, v / U_s, (T - T_ref) / dT, phi) -> LBM init fields
-// [n][phi | ux | uy | T][y][x] in float64; phi clipped to [0, 1].
-__global__ __launch_bounds__(256) void to_fields_kernel(const ChanDesc* desc, const float* pred, double* fields, int n, int h, int w) {
+// [n][phi | ux | uy | T][y][x] in float64.  phi: the network's, clipped to
+// [0, 1] (phi_net != 0), or the cold-start tanh profile.
+__global__ __launch_bounds__(256) void to_fields_kernel(const ChanDesc* desc, const float* pred, double* fields, int n, int h, int w,
+                                                        int phi_net) {
     const long long total = (long long)n * h * w;
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
     if (k >= total) return;
@@ -383,8 +405,13 @@ __global__ __launch_bounds__(256) void to_fields_kernel(const ChanDesc* desc, co
     const long long q = k - b * hw;
     const ChanDesc& d = desc[b];
     const float* p = pred + (size_t)k * 4;
-    double ph = (double)p[3];
-    ph = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
+    double ph;
+    if (phi_net) {
+        ph = (double)p[3];
+        ph = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
+    } else {
+        ph = phi_tanh(d, (int)(q / w));
+    }
     double* o = fields + (size_t)b * 4 * hw;
     o[q] = ph;
     o[hw + q] = (double)p[0] * d.U_s;
@@ -413,7 +440,7 @@ __global__ __launch_bounds__(256) void targets_kernel(const ChanDesc* desc, cons
 static inline unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
-    const unsigned grid = (unsigned)((long long)a.n * a.h * (a.w / 64));
+    const unsigned grid = (unsigned)(((long long)a.n * a.h * (a.w / 64) + 3) / 4);
     switch (a.co / 16) {
         case 2: conv_fwd_kernel<2><<<grid, 256, 0, st>>>(a); break;
         case 4: conv_fwd_kernel<4><<<grid, 256, 0, st>>>(a); break;
@@ -478,8 +505,9 @@ hipError_t launch_features(const ChanDesc* d, uint16_t* x, int n, int h, int w, 
     return hipGetLastError();
 }
 
-hipError_t launch_to_fields(const ChanDesc* d, const float* pred, double* fields, int n, int h, int w, hipStream_t st) {
-    to_fields_kernel<<<blocks_of((long long)n * h * w), 256, 0, st>>>(d, pred, fields, n, h, w);
+hipError_t launch_to_fields(const ChanDesc* d, const float* pred, double* fields, int n, int h, int w, int phi_net,
+                            hipStream_t st) {
+    to_fields_kernel<<<blocks_of((long long)n * h * w), 256, 0, st>>>(d, pred, fields, n, h, w, phi_net);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ def load():
     L.nn_adam.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i32, i64, f32, f32, f32, f32, f32, vp]
     L.nn_cast_weights.argtypes = [vp, vp, vp, i32, i32, vp]
     L.nn_features.argtypes = [pp, i32, vp, i32, vp]
-    L.nn_to_fields.argtypes = [pp, i32, vp, vp, vp]
+    L.nn_to_fields.argtypes = [pp, i32, vp, vp, i32, vp]
     L.nn_targets.argtypes = [pp, i32, vp, vp, vp]
     L.nn_velocity_scale.argtypes = [pp]
     L.nn_velocity_scale.restype = ctypes.c_double
@@ -126,8 +126,9 @@ def nn_features(cfgs, x, cpad):
     _check(load().nn_features(_params(cfgs), len(cfgs), _p(x), int(cpad), _stream()), "nn_features")
 
 
-def nn_to_fields(cfgs, pred, fields):
-    _check(load().nn_to_fields(_params(cfgs), len(cfgs), _p(pred), _p(fields), _stream()), "nn_to_fields")
+def nn_to_fields(cfgs, pred, fields, phi_from_net=False):
+    _check(load().nn_to_fields(_params(cfgs), len(cfgs), _p(pred), _p(fields), int(bool(phi_from_net)), _stream()),
+           "nn_to_fields")
 
 
 def nn_targets(cfgs, fields, target):

@@ -13,12 +13,12 @@ loops over mini-batches.
 
 Network (NHWC, channels padded to multiples of 32; every conv 3x3 + bias,
 ReLU except the last; x periodic, zero padding in y):
-  level 0 (ny x nx):  c0 8(->32) -> 32, c1 32 -> 32            s0 = c1
+  level 0 (ny x nx):  c0 10(->32) -> 32, c1 32 -> 32           s0 = c1
   level 1 (1/2):      c2 32 -> 64, c3 64 -> 64                  s1 = c3
   level 2 (1/4):      c4 64 -> 96, c5 96 -> 96
   level 1:            c6 96 -> 64 on up(c5); a1 = c6 + s1; c7 64 -> 64
   level 0:            c8 64 -> 32 on up(c7); a0 = c8 + s0; c9 32 -> 4(->32), linear
-About 316k real parameters.  Inputs: 8 planes (nn_features); outputs
+About 317k real parameters.  Inputs: 10 planes (nn_features); outputs
 u / U_s, v / U_s, (T - T_ref) / dT, phi.
 """
 from __future__ import annotations
@@ -31,7 +31,7 @@ import numpy as np
 from . import inputs, lbm, nn
 
 CPAD = 32            # padded input / output channel count
-NFEAT = 8            # real input planes
+NFEAT = 10           # real input planes
 NOUT = 4             # real outputs
 # name: (ci_pad, ci_real, co_pad, co_real, level)
 LAYERS = {
@@ -257,8 +257,9 @@ class WarmStartNet:
         nn.nn_features(cfgs, x, CPAD)
         return x
 
-    def predict_fields(self, cfgs, batch: int = 32):
-        """Device float64 fields [n][phi|ux|uy|T][ny][nx] for lbm_init_device."""
+    def predict_fields(self, cfgs, batch: int = 32, phi_from_net: bool = False):
+        """Device float64 fields [n][phi|ux|uy|T][ny][nx] for lbm_init_device
+        (phi: the cold-start profile unless phi_from_net)."""
         t = self.torch
         ny, nx = int(cfgs[0]["ny"]), int(cfgs[0]["nx"])
         out = t.empty((len(cfgs), 4, ny, nx), dtype=t.float64, device=self.dev)
@@ -266,7 +267,7 @@ class WarmStartNet:
             part = cfgs[s:s + batch]
             x = self.features(part)
             y = self.forward(x, len(part), ny, nx)
-            nn.nn_to_fields(part, y, out[s:s + len(part)])
+            nn.nn_to_fields(part, y, out[s:s + len(part)], phi_from_net)
         return out
 
 
@@ -349,7 +350,7 @@ def train(net, X, Y, epochs, batch=16, lr=2e-3, lr_min=2e-5, warmup=100, seed=0,
     return hist
 
 
-def relative_errors(pred, ref):
+def relative_errors(pred, ref, T_ref=1.0):
     """Per-output relative L2 errors of [n][4][ny][nx] fields (phi, ux, uy, T):
     phi, and T - T_ref, relative to their own norms; u, v relative to |u|."""
     import torch
@@ -361,7 +362,7 @@ def relative_errors(pred, ref):
         if name in ("ux", "uy"):
             den = unorm
         elif name == "T":
-            den = torch.sqrt(torch.sum((ref[:, 3] - 1.0) ** 2, dim=(1, 2)))
+            den = torch.sqrt(torch.sum((ref[:, 3] - T_ref) ** 2, dim=(1, 2)))
         else:
             den = torch.sqrt(torch.sum(ref[:, 0] ** 2, dim=(1, 2)))
         out[name] = (d / den).cpu().numpy()

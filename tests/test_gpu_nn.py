@@ -171,10 +171,12 @@ def test_features_targets_and_handoff(env):
                   np.broadcast_to(((c["mu_a"] + ph * (c["mu_b"] - c["mu_a"])) / c["mu_b"])[:, None], (ny, nx)),
                   np.broadcast_to(((c["k_a"] + ph * (c["k_b"] - c["k_a"])) / c["k_b"])[:, None], (ny, nx)),
                   np.full((ny, nx), c["sigma_T"] / 2e-4), np.full((ny, nx), c["sigma_TT"] / 3e-4),
-                  np.broadcast_to(((j + 0.5) / ny)[:, None], (ny, nx)), np.full((ny, nx), c["b"] / ny)]
+                  np.broadcast_to(((j + 0.5) / ny)[:, None], (ny, nx)), np.full((ny, nx), c["b"] / ny),
+                  np.full((ny, nx), np.log(c["mu_a"] / c["mu_b"]) / np.log(5.0)),
+                  np.full((ny, nx), np.log(c["k_a"] / c["k_b"]) / np.log(5.0))]
         for q, pl in enumerate(planes):
             assert np.allclose(X[k, :, :, q], pl, rtol=2.0 ** -8, atol=1e-7), (k, q)
-        assert np.all(X[k, :, :, 8:] == 0)
+        assert np.all(X[k, :, :, 10:] == 0)
     rng = np.random.default_rng(13)
     F = np.stack([np.stack([np.clip(rng.uniform(-0.1, 1.1, (ny, nx)), 0, 1), rng.normal(0, 1e-5, (ny, nx)),
                             rng.normal(0, 1e-5, (ny, nx)), 1 + rng.normal(0, 0.3, (ny, nx))]) for _ in range(3)])
@@ -182,7 +184,7 @@ def test_features_targets_and_handoff(env):
     tgt = torch.empty((3, ny, nx, 4), dtype=torch.float32, device="cuda")
     nn.nn_targets(cfgs, Fd, tgt)
     back = torch.empty_like(Fd)
-    nn.nn_to_fields(cfgs, tgt, back)
+    nn.nn_to_fields(cfgs, tgt, back, phi_from_net=True)
     # the targets are float32: each field comes back to float32 rounding of its scale
     Bk = back.cpu().numpy()
     for c in range(4):
@@ -192,6 +194,14 @@ def test_features_targets_and_handoff(env):
         us = nn.nn_velocity_scale(c)
         assert us == pytest.approx(0.01 * (abs(c["sigma_T"]) + c["sigma_TT"]) / c["mu_b"], rel=1e-12)
         assert np.allclose(tgt.cpu().numpy()[k, :, :, 0], F[k, 1] / us, rtol=1e-6, atol=1e-6)
+    # default hand-off: the cold-start phi profile, the network's u, v, T
+    cold = torch.empty_like(Fd)
+    nn.nn_to_fields(cfgs, tgt, cold)
+    Ch = cold.cpu().numpy()
+    for k, c in enumerate(cfgs):
+        ph = 0.5 * (1 + np.tanh(2 * ((c["b"] - 0.5) - np.arange(ny)) / c["W"]))
+        assert np.allclose(Ch[k, 0], np.broadcast_to(ph[:, None], (ny, nx)), rtol=0, atol=1e-15)
+        assert np.array_equal(Ch[k, 1:], back.cpu().numpy()[k, 1:])
     for prec in (0, 1):
         a = lbm.lbm_create(cfgs, precision=prec)
         b = lbm.lbm_create(cfgs, precision=prec)
@@ -215,7 +225,7 @@ def test_network_gradients_against_oracle(env):
     for name in ws.LAYERS:
         net.p[name]["b"].copy_(torch.from_numpy(rng.normal(0, 0.1, net.p[name]["b"].shape[0]).astype(np.float32)))
     x = torch.zeros((n, h, w, 32), dtype=torch.bfloat16, device="cuda")
-    x[..., :8] = torch.from_numpy(rng.normal(size=(n, h, w, 8)).astype(np.float32)).cuda().to(torch.bfloat16)
+    x[..., :10] = torch.from_numpy(rng.normal(size=(n, h, w, 10)).astype(np.float32)).cuda().to(torch.bfloat16)
     tgt = rng.normal(size=(n, h, w, 4)).astype(np.float32)
     net.forward(x, n, h, w)
     loss = float(net.loss_grad(f32(torch, tgt), n, h, w).cpu()[0])
