@@ -47,6 +47,8 @@ struct lbm_ctx {
     void* twall = nullptr;             // bottom-wall temperature by column
     float* tref = nullptr;             // per-node temperature reference (float32 mode)
     float* tref_new = nullptr;         // references written by a check step
+    int32_t* dl = nullptr;             // per-node phi-reference offsets, units of DL_Q (float32 mode)
+    int32_t* dl_new = nullptr;         // offsets written by a check step
     double* snap = nullptr;            // 4 * total_nodes
     double* partials = nullptr;        // n_tiles * 8 (capacity for the smallest tile)
     int partial_cap = 0;
@@ -201,6 +203,8 @@ void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
     a.fr_v = c->fr;
     a.tref_v = c->tref;
     a.tref_out = c->tref_new;
+    a.dl_v = c->dl;
+    a.dl_out = c->dl_new;
     for (int k = 0; k < 4; ++k) a.snap[k] = c->snap + (size_t)k * c->total_nodes;
     a.partials = c->partials;
     for (int k = 0; k < 5; ++k) a.out[k] = nullptr;
@@ -226,11 +230,14 @@ int enqueue_step(lbm_ctx* c, long long s) {
     }
     if (check && c->prec == LBM_FP32_DEV) {
         // the check step stored its populations relative to new temperature
-        // references; make those current (before the check may retire a channel)
+        // and phi references; make those current (before the check may retire
+        // a channel)
         TrefArgs r;
         r.insts = c->d_inst;
         r.tref = c->tref;
         r.tref_new = c->tref_new;
+        r.dl = c->dl;
+        r.dl_new = c->dl_new;
         hipError_t e = launch_tref_copy(r, c->max_nodes, c->n_inst, c->stream);
         if (e != hipSuccess) return fail_hip(c, e, "reference copy launch");
     }
@@ -384,7 +391,9 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     if (precision == LBM_FP32_DEV) {
         c->tref = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
         c->tref_new = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
-        if (!c->tref || !c->tref_new) rc = LBM_ENOMEM;
+        c->dl = (int32_t*)dev_alloc(c, (size_t)nodes * sizeof(int32_t));
+        c->dl_new = (int32_t*)dev_alloc(c, (size_t)nodes * sizeof(int32_t));
+        if (!c->tref || !c->tref_new || !c->dl || !c->dl_new) rc = LBM_ENOMEM;
     }
     c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
     c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
@@ -609,6 +618,7 @@ static int init_impl(lbm_ctx* c, const double* fields, bool device) {
     a.fq_v = c->fq;
     a.tw_v = c->twall;
     a.tref = c->tref;
+    a.dl = c->dl;
     a.cold = fields ? 0 : 1;
     double* dfields = nullptr;
     if (fields) {
@@ -794,6 +804,7 @@ static int state_io(lbm_ctx* c, int32_t inst, double* host, int dir) {
     a.fq_v = c->fq;
     a.tw_v = c->twall;
     a.tref = c->tref;
+    a.dl = c->dl;
     a.state = d;
     if (dir == 1) HIPCHK(c, hipMemcpyAsync(d, host, sizeof(double) * 27 * n, hipMemcpyHostToDevice, c->stream));
     hipError_t e = launch_state(c->prec, a, (int)n, c->stream);

@@ -18,6 +18,12 @@ constexpr int TILE_SHAPES[N_TILE_SHAPES][2] = {{64, 8}, {32, 8}, {64, 4}, {16, 1
 // Regularisation of the interface normal where grad phi vanishes:
 // n = grad phi / sqrt(|grad phi|^2 + EPS_N^2).
 constexpr double EPS_N = 1e-6;
+// Float32 mode: the per-node phi-reference offset is k DL_Q with integer k.
+// With weights w = m / 36 (m = 16, 4, 1) every w dl is the integer m k times
+// 2^-28, so the reference mass that pullers add back sums exactly (integer
+// arithmetic) to the mass that writers removed.
+constexpr double DL_U = 1.0 / 268435456.0;   // 2^-28
+constexpr double DL_Q = 36.0 * DL_U;
 
 // Per-channel descriptor in device memory.
 struct Inst {
@@ -54,6 +60,8 @@ struct StepArgs {
     const void* fr_v;             // constant part of the stored post-collision y-moment of f, by row
     const void* tref_v;           // per-node temperature reference (float32 mode)
     void* tref_out;               // new references written by a check step
+    const int32_t* dl_v;          // per-node phi-reference offset from phi0(row), in units of DL_Q (float32 mode)
+    int32_t* dl_out;              // new offsets written by a check step
     double* snap[4];              // ux, uy, T, phi at the last check
     double* partials;             // [tile][8]
     double* out[5];               // fields: phi, ux, uy, T, p
@@ -75,6 +83,7 @@ struct InitArgs {
     const void* fq_v;
     const void* tw_v;
     float* tref;
+    int32_t* dl;                  // phi-reference offsets, units of DL_Q (float32 mode)
     const double* fields[4];      // phi, ux, uy, T (device), when not cold
     int cold;
 };
@@ -88,6 +97,7 @@ struct StateArgs {
     const void* fq_v;
     const void* tw_v;
     const float* tref;
+    const int32_t* dl;
     double* state;                // device [3][9][ny][nx] float64
 };
 
@@ -95,6 +105,8 @@ struct TrefArgs {
     const Inst* insts;
     float* tref;
     const float* tref_new;
+    int32_t* dl;
+    const int32_t* dl_new;
 };
 
 hipError_t launch_step(int prec, const StepArgs& a, int mode, int grid, int tx, int ty, hipStream_t st);

@@ -255,6 +255,8 @@ void step_kernel(StepArgs a) {
 
     __shared__ R s_phb[LY2 * LX2];  // phi - phi0(row)
     __shared__ R s_Tr[LY2 * LX2];   // temperature reference (float32 mode)
+    constexpr int LX3 = TX + 6, LY3 = TY + 6;   // phi-reference offset region (halo 3)
+    __shared__ int32_t s_dl[DEV ? LY3 * LX3 : 1];   // phi reference minus phi0(row), units of DL_Q
     __shared__ R s_Tb[LY1 * LX1];   // T - Tr
     __shared__ R s_pb[LY1 * LX1];   // p* - p_r
     __shared__ R s_nx[LY1 * LX1];
@@ -315,11 +317,17 @@ void step_kernel(StepArgs a) {
         s_fq[k] = DEV ? ((const R*)a.fq_v)[r] : R(0);
     }
     if (DEV) {
+        // per-node references: phi offsets on tile + 3, temperatures on tile + 2
+        const int32_t* __restrict__ dlv = a.dl_v + I.node_off;
         const R* __restrict__ tref = (const R*)a.tref_v + I.node_off;
-        for (int k = tid; k < LY2 * LX2; k += NT) {
-            const int hy = k / LX2 - 2, hx = k % LX2 - 2;
+        for (int k = tid; k < LY3 * LX3; k += NT) {
+            const int hy = k / LX3 - 3, hx = k % LX3 - 3;
             const int jj = y0 + hy;
-            s_Tr[k] = (jj >= 0 && jj < ny) ? tref[(uint32_t)jj * (uint32_t)nx + (uint32_t)colwrap(x0 + hx)] : R(0);
+            const bool in = jj >= 0 && jj < ny;
+            const uint32_t o = in ? (uint32_t)jj * (uint32_t)nx + (uint32_t)colwrap(x0 + hx) : 0u;
+            s_dl[k] = in ? dlv[o] : 0;
+            if (hy >= -2 && hy <= TY + 1 && hx >= -2 && hx <= TX + 1)
+                s_Tr[(hy + 2) * LX2 + hx + 2] = in ? tref[o] : R(0);
         }
     }
     __syncthreads();
@@ -328,6 +336,25 @@ void step_kernel(StepArgs a) {
         const R g0 = R(0.5) * (s_phi0[k + 2] - s_phi0[k]);
         s_n0y[k] = DEV ? g0 / sqrt(g0 * g0 + R(EPS_N * EPS_N)) : R(0);
     }
+    // phi-reference moments of the f populations streamed into node (hx,
+    // hy): each is stored relative to w_a (phi0(row) + dl(writer)), so the
+    // node adds sum_a w_a e_a^m dl(source) (m = 0, x, y), summed exactly in
+    // integers (units of 2^-28).  The source of a wall link is the writer in
+    // the node's own row (specular reflection).
+    auto fcorr = [&](int hx, int hy, int jj, int& c0, int& cx, int& cy) {
+        c0 = 0; cx = 0; cy = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int ex = EX(q), ey = EY(q);
+            const bool wall = ey != 0 && (jj - ey < 0 || jj - ey >= ny);
+            const int sy = wall ? hy : hy - ey, sx = hx - ex;
+            const int m = q == 0 ? 16 : (q < 5 ? 4 : 1);          // 36 w_q
+            const int d = m * s_dl[(sy + 3) * LX3 + sx + 3];
+            c0 += d;
+            if (ex) cx += ex > 0 ? d : -d;
+            if (ey) cy += ey > 0 ? d : -d;
+        }
+    };
     // Temperature-reference moments of the populations streamed into node
     // (hx, hy): each is stored relative to its writer's reference, so the
     // node sees sum_a w_a e_a^m (Tr(source) - Tr(node)) on top of its own.
@@ -369,7 +396,11 @@ void step_kernel(StepArgs a) {
             // sum phi up to the rounding of one small stored value.  rf[1]
             // stays the y-moment of the stored deviations alone: the
             // references' share of it is folded into the fr table.
-            dph_d = (double)s_dR[ty + 2] + ((double)s_fq[ty + 2] - (double)s_fq[ty + 4]);
+            int d0, dxm, dym;
+            fcorr(tx, ty, gj, d0, dxm, dym);
+            rf[3] += (R)((double)dxm * DL_U);
+            rf[1] += (R)((double)dym * DL_U);
+            dph_d = (double)s_dR[ty + 2] + ((double)s_fq[ty + 2] - (double)s_fq[ty + 4]) + (double)d0 * DL_U;
 #pragma unroll
             for (int q = 0; q < 9; ++q) dph_d += (double)f[q];
             rf[0] = (R)dph_d;
@@ -398,7 +429,9 @@ void step_kernel(StepArgs a) {
                 R c0, cx, cy;
                 tcorr(hx, hy, jj, c0, cx, cy);
                 s3 += c0;
-                s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]);
+                int i0, ix, iy;
+                fcorr(hx, hy, jj, i0, ix, iy);
+                s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]) + (R)((double)i0 * DL_U);
             }
             s_phb[(hy + 2) * LX2 + hx + 2] = s1;
             s_pb[(hy + 1) * LX1 + hx + 1] = s2;
@@ -408,7 +441,11 @@ void step_kernel(StepArgs a) {
             R s1 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) s1 += tf[q];
-            if (DEV) s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]);
+            if (DEV) {
+                int i0, ix, iy;
+                fcorr(hx, hy, jj, i0, ix, iy);
+                s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]) + (R)((double)i0 * DL_U);
+            }
             s_phb[(hy + 2) * LX2 + hx + 2] = s1;
         }
     }
@@ -598,7 +635,25 @@ void step_kernel(StepArgs a) {
             // float32 mode)
             {
                 const R ph0 = s_phi0[ty + 2];
-                const R dph = phb;                                // phi - phi0
+                const R dph = phb;                                // phi - phi0(row)
+                // this node's storage reference phr = phi0(row) + dl (float32
+                // mode); a check step moves it to the current phi when the node
+                // has drifted by more than 1e-6, so that near steady state the
+                // stored values stay small
+                R phr = ph0, dphr = dph;
+                double dphr_d = dph_d;
+                if (DEV) {
+                    int32_t kdl = s_dl[(ty + 3) * LX3 + tx + 3];
+                    if (MODE == 1) {
+                        const double dd = dph_d - (double)kdl * DL_Q;
+                        if (dd > 1e-6 || dd < -1e-6) kdl = (int32_t)llrint(dph_d / DL_Q);
+                        if (own_ok) a.dl_out[(size_t)I.node_off + (size_t)gj * nx + gi] = kdl;
+                    }
+                    const double dlo = (double)kdl * DL_Q;
+                    phr = (R)((double)ph0 + dlo);
+                    dphr_d = dph_d - dlo;
+                    dphr = (R)dphr_d;
+                }
                 const R k10 = rf[3] - ux * phi;
                 const R theta = R(4) * phi * (R(1) - phi) * p.inv_W;
                 R t01;
@@ -616,17 +671,17 @@ void step_kernel(StepArgs a) {
                     t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
                 }
                 const R t10 = k10 + p.w_phi * (p.M * theta * nxv - k10);
-                // post-collision central moments minus ph0 * (rest central moments)
+                // post-collision central moments minus phr * (rest central moments)
                 R c[9];
-                c[0] = dph;                                  // 00
-                c[1] = t01 + ph0 * uy;                       // 01
-                c[2] = dph * cs2 - ph0 * uy2;                // 02
-                c[3] = t10 + ph0 * ux;                       // 10
-                c[4] = -ph0 * uxy;                           // 11
-                c[5] = ph0 * ux * (cs2 + uy2);               // 12
-                c[6] = dph * cs2 - ph0 * ux2;                // 20
-                c[7] = ph0 * uy * (cs2 + ux2);               // 21
-                c[8] = dph * (cs2 * cs2) - ph0 * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
+                c[0] = dphr;                                 // 00
+                c[1] = t01 + phr * uy;                       // 01
+                c[2] = dphr * cs2 - phr * uy2;               // 02
+                c[3] = t10 + phr * ux;                       // 10
+                c[4] = -phr * uxy;                           // 11
+                c[5] = phr * ux * (cs2 + uy2);               // 12
+                c[6] = dphr * cs2 - phr * ux2;               // 20
+                c[7] = phr * uy * (cs2 + ux2);               // 21
+                c[8] = dphr * (cs2 * cs2) - phr * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
                 if (DEV) {
                     // minus the other central moments of q (raw: m01 = A only)
                     const R A = R(2) * s_fq[ty + 3];
@@ -640,11 +695,11 @@ void step_kernel(StepArgs a) {
                 raw_to_dist(c, f);
                 if (DEV) {
                     // the rest population takes the rounding of the other
-                    // eight: the stored values sum to phi - phi0 in float64
+                    // eight: the stored values sum to phi - phr in float64
                     double s8 = 0.0;
 #pragma unroll
                     for (int q = 1; q < 9; ++q) s8 += (double)f[q];
-                    f[0] = (R)(dph_d - s8);
+                    f[0] = (R)(dphr_d - s8);
                 }
             }
             // --- energy (Sec. 4.3), stored as h - w Tr(this node) ---
@@ -877,6 +932,17 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     central_to_raw(ch, ux, uy); raw_to_dist(ch, eh);
     const R* phi0 = (const R*)a.phi0_v + I.row_off + 2;
     const R* fq = (const R*)a.fq_v + I.row_off + 2;
+    // phi-reference offset of the writer at (ii, jj): phi there minus phi0(row),
+    // rounded as the step kernel stores it (float32 mode)
+    auto kdl_at = [&](int ii, int jj) -> int32_t {
+        if (!DEV) return 0;
+        double ph;
+        if (a.cold) ph = 0.5 * (1.0 + tanh(2.0 * ((I.b - 0.5) - (double)jj) / I.W));
+        else ph = a.fields[0][(size_t)I.node_off + (size_t)jj * I.nx + ii];
+        return (int32_t)llrint((ph - (double)phi0[jj]) / DL_Q);
+    };
+    auto dl_at = [&](int ii, int jj) { return (double)kdl_at(ii, jj) * DL_Q; };
+    if (DEV) a.dl[I.node_off + q] = kdl_at(i, j);
     // flux reference of direction k written at row r (float32 mode)
     auto qf = [&](int kk, int r) { return (DEV && EX(kk) == 0 && EY(kk) != 0) ? EY(kk) * (double)fq[r] : 0.0; };
     const double pr = DEV ? I.p_r : 0.0;
@@ -893,14 +959,14 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         if (js >= 0 && js < ny) {
             const double ph_w = DEV ? (double)phi0[js] : 0.0;
             const double T_w = DEV ? (double)(float)init_T_src(a, I, is, js, twr) : 0.0;
-            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k] - w * ph_w - qf(k, js));
+            dst[pidx(nx, ny, 0, k, js, is)] = S(ef[k] - w * (ph_w + dl_at(is, js)) - qf(k, js));
             dst[pidx(nx, ny, 1, k, js, is)] = S(eg[k] - w * pr);
             dst[pidx(nx, ny, 2, k, js, is)] = S(eh[k] - w * T_w);
         } else {
             const int mir = MIRY(k), opp = OPP(k);
             const double Tw = (ey > 0) ? tw_at(i) : I.T_c;
             const double ph_w = DEV ? (double)phi0[j] : 0.0;
-            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k] - w * ph_w - qf(mir, j));
+            dst[pidx(nx, ny, 0, mir, j, is)] = S(ef[k] - w * (ph_w + dl_at(is, j)) - qf(mir, j));
             dst[pidx(nx, ny, 1, opp, j, i)] = S(eg[k] - w * pr);
             // anti-bounce-back: h_k = -(stored + w Tr_self) + 2 w T_w
             dst[pidx(nx, ny, 2, opp, j, i)] = S(2.0 * w * Tw - w * Tr_self - eh[k]);
@@ -935,13 +1001,13 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
         double ref_f, ref_h, sgn_h = 1.0, add_h = 0.0;
         if (js >= 0 && js < ny) {
             kf = pidx(nx, ny, 0, k, js, is); kg = pidx(nx, ny, 1, k, js, is); kh = pidx(nx, ny, 2, k, js, is);
-            ref_f = DEV ? w * (double)phi0[js] + qf(k, js) : 0.0;
+            ref_f = DEV ? w * ((double)phi0[js] + (double)a.dl[I.node_off + (size_t)js * nx + is] * DL_Q) + qf(k, js) : 0.0;
             ref_h = DEV ? w * (double)tref[(size_t)js * nx + is] : 0.0;
         } else {
             const int mir = MIRY(k), opp = OPP(k);
             const double Tw = (ey > 0) ? (double)tw[i] : I.T_c;
             kf = pidx(nx, ny, 0, mir, j, is); kg = pidx(nx, ny, 1, opp, j, i); kh = pidx(nx, ny, 2, opp, j, i);
-            ref_f = DEV ? w * (double)phi0[j] + qf(mir, j) : 0.0;
+            ref_f = DEV ? w * ((double)phi0[j] + (double)a.dl[I.node_off + (size_t)j * nx + is] * DL_Q) + qf(mir, j) : 0.0;
             // h_k = -(stored + w Tr_self) + 2 w T_w
             sgn_h = -1.0;
             ref_h = 0.0;
@@ -973,6 +1039,7 @@ __global__ __launch_bounds__(256) void tref_copy_kernel(TrefArgs a) {
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     if (q >= n) return;
     a.tref[I.node_off + q] = a.tref_new[I.node_off + q];
+    a.dl[I.node_off + q] = a.dl_new[I.node_off + q];
 }
 
 // ---------------------------------------------------------------------------
