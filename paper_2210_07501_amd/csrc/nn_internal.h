@@ -7,7 +7,6 @@
 namespace nn {
 
 constexpr int MAX_CH = 96;               // widest layer (channels, padded to 32)
-constexpr int MAX_TILES_PER_WAVE = 9;    // (96 / 16)^2 weight-gradient tiles over 4 waves
 constexpr int NFEAT = 10;                // input planes
 
 // Per-channel description for the feature and hand-off kernels.

@@ -111,84 +111,112 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a) {
 
 // ---------------------------------------------------------------------------
 // Weight gradient dW[co][t][ci] = sum_p dY[p][co] X[nbr(p, t)][ci] and bias
-// gradient, split over pixel chunks: block (chunk, tap) stages 64 pixels of
-// dY and of the tap-shifted X through LDS transposed to [channel][pixel], so
-// that MFMA fragments (8 consecutive pixels of one channel) are contiguous.
+// gradient, split over pixel chunks.  Block (chunk, dy) covers the three taps
+// of one neighbour row.  Per step of 64 pixels (one row segment: w % 64 == 0
+// and chunks start on multiples of 64) it stages dY once and the input row at
+// the three x shifts, both transposed to [channel][pixel] in LDS so that MFMA
+// fragments (8 consecutive pixels of one channel) are single 16-byte reads.
+// Staging uses 16-byte global loads and packs pixel pairs into 32-bit LDS
+// writes.  Wave w owns the GEMM columns (tap, 16-channel input group) w,
+// w + 4, ... for every output-channel tile: per half step it reads the dY
+// fragments once and each input fragment once for all output tiles.
 // Partial sums go to work[chunk][co][9][ci] (and work_b[chunk][co]); a second
 // kernel adds the chunks in a fixed order.
-constexpr int WG_PIX = 64;                  // pixels per K step (two MFMA K=32)
-constexpr int LDS_PAD = 8;                  // row padding (bf16) against bank conflicts
+constexpr int WG_PIX = 64;                  // pixels per step (two MFMA K=32)
+constexpr int LS = WG_PIX + 8;              // LDS row stride (bf16), 16-byte multiple
 
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+template <int CO, int CI>
 __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgradArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t s_dy[MAX_CH * (WG_PIX + LDS_PAD)];
-    __shared__ __attribute__((aligned(16))) uint16_t s_x[MAX_CH * (WG_PIX + LDS_PAD)];
-    const int chunk = blockIdx.x, t = blockIdx.y;
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    constexpr int MT = CO / 16, NJ = CI / 16, NCOL = 3 * NJ, MAXC = (NCOL + 3) / 4;
+    __shared__ __attribute__((aligned(16))) uint16_t s_dy[CO * LS];
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[3 * CI * LS];
+    const int chunk = blockIdx.x, dy = (int)blockIdx.y - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, li = lane & 15;
-    const int co = a.co, ci = a.ci;
-    const int mt = co >> 4, ntl = ci >> 4, ntiles = mt * ntl;
-    constexpr int LS = WG_PIX + LDS_PAD;
-    // tiles of this wave: wave, wave + 4, ... (at most MAX_TILES_PER_WAVE)
-    f32x4 acc[MAX_TILES_PER_WAVE];
+    f32x4 acc[MAXC][MT];
 #pragma unroll
-    for (int q = 0; q < MAX_TILES_PER_WAVE; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;   // bias partial of channel threadIdx.x (tap 4 blocks only)
+    for (int c = 0; c < MAXC; ++c)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[c][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;   // bias partial of channel threadIdx.x (centre-row blocks)
     const long long p_begin = (long long)chunk * a.chunk_pix;
     const long long p_end = min(p_begin + a.chunk_pix, a.npix);
     for (long long p0 = p_begin; p0 < p_end; p0 += WG_PIX) {
-        // stage: 64 pixels (one row segment, since w % 64 == 0 and chunks
-        // start on multiples of 64) of dY and of X at the tap's neighbours
         const long long rowp = p0 / a.w;               // n * h + y
         const int x0 = (int)(p0 - rowp * a.w);
         const int y = (int)(rowp % a.h);
-        const int yy = y + dy;
-        const bool inb = yy >= 0 && yy < a.h;
-        for (int e = threadIdx.x; e < WG_PIX * co; e += 256) {
-            const int pp = e / co, c = e - pp * co;
-            s_dy[c * LS + pp] = a.dy[(size_t)(p0 + pp) * co + c];
+        const bool inb = y + dy >= 0 && y + dy < a.h;
+        const size_t xrow = (size_t)(inb ? rowp + dy : rowp) * a.w;
+        // dY: 32 pixel pairs x CO / 8 channel groups
+        for (int e = threadIdx.x; e < 32 * (CO / 8); e += 256) {
+            const int pr = e & 31, g = e >> 5, pp = 2 * pr;
+            const uint4 v0 = *(const uint4*)(a.dy + (size_t)(p0 + pp) * CO + 8 * g);
+            const uint4 v1 = *(const uint4*)(a.dy + (size_t)(p0 + pp + 1) * CO + 8 * g);
+            const uint16_t* h0 = (const uint16_t*)&v0;
+            const uint16_t* h1 = (const uint16_t*)&v1;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) *(uint32_t*)&s_dy[(8 * g + i) * LS + pp] = pack2(h0[i], h1[i]);
         }
-        for (int e = threadIdx.x; e < WG_PIX * ci; e += 256) {
-            const int pp = e / ci, c = e - pp * ci;
-            int xx = x0 + pp + dx;
-            xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
-            s_x[c * LS + pp] = inb ? a.x[((size_t)(rowp + dy) * a.w + xx) * ci + c] : (uint16_t)0;
+        // input row at x shifts -1, 0, +1: destination pair (pp, pp + 1) of
+        // copy dx holds source pixels x0 + pp + dx and x0 + pp + 1 + dx
+        for (int e = threadIdx.x; e < 32 * (CI / 8); e += 256) {
+            const int pr = e & 31, g = e >> 5, pp = 2 * pr;
+            uint4 v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                int xx = x0 + pp - 1 + m;
+                xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
+                v[m] = inb ? *(const uint4*)(a.x + (xrow + xx) * CI + 8 * g) : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const uint16_t* hl = (const uint16_t*)&v[d];
+                const uint16_t* hh = (const uint16_t*)&v[d + 1];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) *(uint32_t*)&s_x[(d * CI + 8 * g + i) * LS + pp] = pack2(hl[i], hh[i]);
+            }
         }
         __syncthreads();
-        if (a.db && t == 4 && (int)threadIdx.x < co) {
+        if (a.db && dy == 0 && (int)threadIdx.x < CO) {
             for (int pp = 0; pp < WG_PIX; ++pp) bsum += b2f(s_dy[threadIdx.x * LS + pp]);
         }
 #pragma unroll
-        for (int q = 0; q < MAX_TILES_PER_WAVE; ++q) {
-            const int tile = wave + 4 * q;
-            if (tile < ntiles) {
-                const int mi = tile / ntl, nj = tile - mi * ntl;
+        for (int hf = 0; hf < WG_PIX / 32; ++hf) {
+            bf16x8 af[MT];
 #pragma unroll
-                for (int h = 0; h < WG_PIX / 32; ++h) {
-                    const bf16x8 av = load8(&s_dy[(16 * mi + li) * LS + 32 * h + 8 * kq]);
-                    const bf16x8 bv = load8(&s_x[(16 * nj + li) * LS + 32 * h + 8 * kq]);
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+            for (int m = 0; m < MT; ++m) af[m] = load8(&s_dy[(16 * m + li) * LS + 32 * hf + 8 * kq]);
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                const int col = wave + 4 * c;
+                if (col < NCOL) {
+                    const int d = col / NJ, nj = col - d * NJ;
+                    const bf16x8 bv = load8(&s_x[(d * CI + 16 * nj + li) * LS + 32 * hf + 8 * kq]);
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[c][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bv, acc[c][m], 0, 0, 0);
                 }
             }
         }
         __syncthreads();
     }
     // partials: work[chunk][co][9][ci]
-    float* wp = a.work + (size_t)chunk * co * 9 * ci;
+    float* wp = a.work + (size_t)chunk * CO * 9 * CI;
 #pragma unroll
-    for (int q = 0; q < MAX_TILES_PER_WAVE; ++q) {
-        const int tile = wave + 4 * q;
-        if (tile < ntiles) {
-            const int mi = tile / ntl, nj = tile - mi * ntl;
+    for (int c = 0; c < MAXC; ++c) {
+        const int col = wave + 4 * c;
+        if (col < NCOL) {
+            const int d = col / NJ, nj = col - d * NJ;
+            const int t = 3 * (dy + 1) + d;
             const int cin = 16 * nj + li;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int cout = 16 * mi + 4 * kq + r;
-                wp[((size_t)cout * 9 + t) * ci + cin] = acc[q][r];
-            }
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) wp[((size_t)(16 * m + 4 * kq + r) * 9 + t) * CI + cin] = acc[c][m][r];
         }
     }
-    if (a.db && t == 4 && (int)threadIdx.x < co) a.work_b[(size_t)chunk * co + threadIdx.x] = bsum;
+    if (a.db && dy == 0 && (int)threadIdx.x < CO) a.work_b[(size_t)chunk * CO + threadIdx.x] = bsum;
 }
 
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(WgradArgs a) {
@@ -450,8 +478,25 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int CO, int CI>
+static void wgrad_launch(const WgradArgs& a, hipStream_t st) {
+    conv_wgrad_kernel<CO, CI><<<dim3((unsigned)a.n_chunks, 3), 256, 0, st>>>(a);
+}
+
 hipError_t launch_conv_wgrad(const WgradArgs& a, hipStream_t st) {
-    conv_wgrad_kernel<<<dim3((unsigned)a.n_chunks, 9), 256, 0, st>>>(a);
+    const int key = (a.co / 32) * 4 + a.ci / 32;
+    switch (key) {
+        case 1 * 4 + 1: wgrad_launch<32, 32>(a, st); break;
+        case 1 * 4 + 2: wgrad_launch<32, 64>(a, st); break;
+        case 1 * 4 + 3: wgrad_launch<32, 96>(a, st); break;
+        case 2 * 4 + 1: wgrad_launch<64, 32>(a, st); break;
+        case 2 * 4 + 2: wgrad_launch<64, 64>(a, st); break;
+        case 2 * 4 + 3: wgrad_launch<64, 96>(a, st); break;
+        case 3 * 4 + 1: wgrad_launch<96, 32>(a, st); break;
+        case 3 * 4 + 2: wgrad_launch<96, 64>(a, st); break;
+        case 3 * 4 + 3: wgrad_launch<96, 96>(a, st); break;
+        default: return hipErrorInvalidValue;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     wgrad_reduce_kernel<<<blocks_of((long long)a.co * 9 * a.ci + a.co), 256, 0, st>>>(a);
