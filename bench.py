@@ -152,7 +152,7 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs a single channel (or a batch of channels) "
+        print("bench.py measures one GPU only: it runs a single channel (or a batch of channels) "
               "on one MI355X and has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

@@ -3,7 +3,7 @@ near-steady fields (u, v, T, phi) of a channel from its wall-heating law and
 properties, trained on steady states that the batched LBM solver itself
 produces.  The LBM then starts from the prediction (lbm_init_device) and must
 still reach the same residual; the cold start from rest remains the
-fallback and the judge of the network's error.
+fallback and the reference for the network's error.
 
 Every tensor operation runs in the library's HIP kernels (include/lbm_nn.h):
 3x3 convolutions forward and backward on BF16 matrix cores with FP32
