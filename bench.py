@@ -71,25 +71,44 @@ def run_gpu(cfg, prec, steps, warmup, tile):
     return dict(nodes=nodes, ms_total=ms, wall_s=wall, kernel_ms=kms, res=res)
 
 
-def cpu_baseline(target_s=15.0):
+def cpu_baseline(target_s=12.0, target_1=6.0):
     """The FP64 oracle, as it stands, on the 256 x 128 sub-run of the same
-    channel geometry (scaled by 1/16), timed on this host's cores."""
+    channel geometry (scaled by 1/16), timed on this host's cores: all
+    threads (the reported value) and one thread."""
     from oracle import oracle as orc
     from paper_2210_07501_amd import inputs
 
     cfg = inputs.throughput_channel(scale=16)
-    o = orc.Oracle(cfg)
-    o.init_cold()
-    t = time.perf_counter()
-    o.step(20)
-    est = (time.perf_counter() - t) / 20
-    n = max(20, int(target_s / max(est, 1e-6)))
-    t = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t
     nodes = cfg["nx"] * cfg["ny"]
-    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=orc.max_threads(), kind="oracle",
-                sample="256x128 sub-run of the throughput channel (1/16 scale), %d steps from rest, %.1f s" % (n, dt))
+
+    def rate(target):
+        o = orc.Oracle(cfg)
+        o.init_cold()
+        t = time.perf_counter()
+        o.step(10)
+        est = (time.perf_counter() - t) / 10
+        n = max(10, int(target / max(est, 1e-6)))
+        t = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t
+        return nodes * n / dt / 1e6, n, dt
+
+    threads = orc.max_threads()
+    v, n, dt = rate(target_s)
+    orc.set_threads(1)
+    v1, n1, dt1 = rate(target_1)
+    orc.set_threads(threads)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=v, unit="MLUPS", cores=threads, kind="oracle",
+                sample="256x128 sub-run of the throughput channel (1/16 scale), %d steps from rest, %.1f s" % (n, dt),
+                single_thread_value=v1, single_thread_sample="%d steps, %.1f s" % (n1, dt1), cpu_model=model)
 
 
 def time_to_steady(n=16, cap=400_000):

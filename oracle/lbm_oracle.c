@@ -566,3 +566,13 @@ int orc_max_threads(void) {
     return 1;
 #endif
 }
+
+/* Thread count of later steps (timing only; the result does not depend on it). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -74,6 +74,8 @@ def lib():
         L.orc_collide_g_node.argtypes = [dp] + [ctypes.c_double] * 9 + [dp]
         L.orc_collide_h_node.argtypes = [dp] + [ctypes.c_double] * 4 + [dp]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -191,3 +193,8 @@ def residual(prev: dict, cur: dict, K: int, T_ref: float) -> float:
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for later steps (timing only; results do not depend on it)."""
+    lib().orc_set_threads(int(n))
