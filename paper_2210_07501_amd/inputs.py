@@ -122,3 +122,28 @@ def perturbed_params(c: dict, seed: int) -> dict:
     d["mu_a"] = float(c["mu_b"]) * float(np.exp(rng.uniform(np.log(0.2), np.log(5.0))))
     d["k_a"] = float(c["k_b"]) * float(np.exp(rng.uniform(np.log(0.2), np.log(5.0))))
     return d
+
+
+def droplet(R: float = 20.0, W: float = 4.0, M_phi: float = 0.02, scale: float = 1.0):
+    """Thermocapillary migration of a droplet (Sec. 5.1): domain 8R x 16R,
+    periodic in x, walls at the bottom (T = 0) and top (T = 32 R / 20, a
+    uniform gradient of 0.1), droplet of radius R (fluid b, phi = 1) at the
+    centre, mu = k = 0.2 in both fluids, sigma0 = 2.5e-3, sigma_T = -1e-4,
+    T_ref at mid-height.  Returns (config, fields) with fields = (phi, ux,
+    uy, T) for lbm_init: fluid at rest, tanh droplet of width W, linear T."""
+    R = R * scale
+    nx, ny = int(round(8 * R)), int(round(16 * R))
+    G = 0.1
+    T_bot, T_top = 0.0, G * ny
+    c = cfg(nx=nx, ny=ny, b=ny / 2.0, W=W, M_phi=M_phi, mu_a=0.2, mu_b=0.2, k_a=0.2, k_b=0.2,
+            sigma0=2.5e-3, sigma_T=-1e-4, sigma_TT=0.0, T_ref=0.5 * (T_bot + T_top),
+            T_h=T_bot, dT=0.0, T_c=T_top)
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    xc, yc = nx / 2.0 - 0.5, ny / 2.0 - 0.5
+    r = np.sqrt((x[None, :] - xc) ** 2 + (y[:, None] - yc) ** 2)
+    phi = 0.5 * (1.0 + np.tanh(2.0 * (R - r) / W))
+    T = np.broadcast_to(T_bot + G * (y[:, None] + 0.5), (ny, nx)).copy()
+    z = np.zeros((ny, nx))
+    return c, (phi, z, z.copy(), T)
+

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import analytic as an
+from paper_2210_07501_amd import inputs
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "printed_numbers.json")))
 
@@ -193,3 +194,17 @@ def test_printed_ygb_velocity():
     Ustar = -g["sigma_T"] * g["gradT"] * g["R"] / g["mu"]
     assert g["rho"] * Ustar * g["R"] / g["mu"] == pytest.approx(g["printed_Re"], rel=1e-9)
     assert Ustar * g["R"] / g["k"] == pytest.approx(g["printed_Ma"], rel=1e-9)
+
+
+def test_regime_boundaries_of_the_closed_form():
+    """a/b = 1, k~ = mu~ = 1, l = 4a: the interface amplitudes of the two
+    harmonics are equal at M2/M1 = 3.57, and the mid-line roll count switches
+    from 4 to 8 between 5.0 and 5.2 -- not at M2 = M1 (reading R15; the
+    paper's map itself is not printed, so this stays parity unpinned)."""
+    def at(r):
+        c = inputs.cfg(nx=256, ny=128, b=64.0, sigma_T=5e-5, sigma_TT=r * 5e-5)
+        ch = an.channel_from_config(c)
+        X, Y = an.lattice_coords(c)
+        return abs(an.U_tt(ch)) / abs(an.U_t(ch)), an.count_rolls(an.velocity(ch, X, Y)[1], c)
+    assert at(3.5)[0] < 1.0 < at(3.6)[0]
+    assert at(2.0)[1] == 4 and at(5.0)[1] == 4 and at(5.2)[1] == 8
