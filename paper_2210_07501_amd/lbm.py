@@ -216,7 +216,9 @@ def lbm_init_device(ctx: _Ctx, fields):
     ptr = fields if isinstance(fields, int) else fields.data_ptr()
     if not isinstance(fields, int):
         need = sum(4 * nx * ny for ny, nx in (ctx.shape(k) for k in range(len(ctx.cfgs))))
-        assert fields.is_cuda and fields.dtype.itemsize == 8 and fields.is_contiguous() and fields.numel() == need
+        if not (fields.is_cuda and fields.dtype.itemsize == 8 and fields.is_floating_point()
+                and fields.is_contiguous() and fields.numel() == need):
+            raise ValueError("lbm_init_device: need a contiguous float64 device tensor of %d values" % need)
     _check(load().lbm_init_device(ctx.h, ctypes.c_void_p(ptr)), "lbm_init_device")
 
 

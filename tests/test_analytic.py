@@ -197,10 +197,11 @@ def test_printed_ygb_velocity():
 
 
 def test_regime_boundaries_of_the_closed_form():
-    """a/b = 1, k~ = mu~ = 1, l = 4a: the interface amplitudes of the two
-    harmonics are equal at M2/M1 = 3.57, and the mid-line roll count switches
-    from 4 to 8 between 5.0 and 5.2 -- not at M2 = M1 (reading R15; the
-    paper's map itself is not printed, so this stays parity unpinned)."""
+    """a/b = 1, k~ = mu~ = 1, l = 4a: the coefficients U_tt and U_t of the two
+    harmonics are equal at M2/M1 = 3.57 (the interface velocity carries
+    U_tt / 2, so its two harmonics are equal at 7.15), and the mid-line roll
+    count switches from 4 to 8 between 5.0 and 5.2 -- not at M2 = M1
+    (reading R15; the paper's map itself is not printed)."""
     def at(r):
         c = inputs.cfg(nx=256, ny=128, b=64.0, sigma_T=5e-5, sigma_TT=r * 5e-5)
         ch = an.channel_from_config(c)
