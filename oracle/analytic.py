@@ -12,6 +12,11 @@ stand.  They equal u = d psi / dy, v = -d psi / dx of
 psi = U_t [C2 y cosh wy + (C3 + C4 y) sinh wy] sin wx
     + U_tt/2 [D2 y cosh 2wy + (D3 + D4 y) sinh 2wy] sin 2wx,
 which is divergence-free; the tests check that and the boundary conditions.
+
+Two results here are not printed in the paper but follow from its solution:
+the Stokes pressure of each layer, and the interface shape to first order in
+the capillary number (the paper keeps the interface flat).  Both are pinned
+by the tests against the momentum and normal-stress balances they solve.
 """
 from __future__ import annotations
 
@@ -151,6 +156,59 @@ def interface_velocity(c: Channel, x):
     return U_t(c) * np.sin(c.omega * x) + 0.5 * U_tt(c) * np.sin(2 * c.omega * x)
 
 
+def pressure(c: Channel, x, y):
+    """Stokes pressure of the Sec. 2 flow, grad p = mu_gamma lap u in each
+    layer.  For a stream-function term A F(y) sin kx with
+    F = C2 y cosh ky + (C3 + C4 y) sinh ky, lap psi = 2 k A (C2 sinh ky +
+    C4 cosh ky) sin kx, so p = -2 mu k A (C2 cosh ky + C4 sinh ky) cos kx
+    (first harmonic: k = w, A = U_t; second: k = 2w, A = U_tt / 2).  Each
+    layer's pressure is defined up to its own constant, taken as 0 here."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    w = c.omega
+    Ut, Utt = U_t(c), U_tt(c)
+    C, D = constants(c)
+    out = []
+    for key, mu in (("a", c.mu_b * c.mu_ratio), ("b", c.mu_b)):
+        _, C2, _, C4 = C[key]
+        _, D2, _, D4 = D[key]
+        out.append(-2 * mu * w * Ut * (C2 * np.cosh(w * y) + C4 * np.sinh(w * y)) * np.cos(w * x)
+                   - 2 * mu * w * Utt * (D2 * np.cosh(2 * w * y) + D4 * np.sinh(2 * w * y)) * np.cos(2 * w * x))
+    return np.where(y >= 0, out[0], out[1])
+
+
+def surface_tension(c: Channel, sigma0: float, T):
+    """Eq. (ST_SRF): sigma(T) = sigma0 + sigma_T (T - T_ref) + sigma_TT (T - T_ref)^2."""
+    d = np.asarray(T, dtype=np.float64) - c.T_ref
+    return sigma0 + c.sigma_T * d + c.sigma_TT * d * d
+
+
+def small_deformation(c: Channel, sigma0: float, n: int = 4096):
+    """Interface height h(x) to first order in the capillary number (not in
+    the paper, which treats the interface as flat; it follows from the flat
+    solution's normal stresses).  With fluid b below and n = +y, the normal
+    stress balance on y = h(x) reads, to first order,
+        sigma(T(x, 0)) (-h'') = (p_b - p_a)(x, 0) - 2 (mu_b - mu_a) dv/dy(x, 0) + c0,
+    where dv/dy(x, 0) = -du/dx of the interface velocity (the same on both
+    sides), c0 is the undetermined difference of the layers' pressure levels,
+    fixed by h' being periodic (h'' of zero mean), and h has zero mean (each
+    layer keeps its volume).  Returns (x, h) on n points of one wavelength."""
+    x = np.arange(n) * (c.l / n)
+    w = c.omega
+    zero = np.zeros_like(x)
+    jump = pressure(c, x, zero - 1e-300) - pressure(c, x, zero)
+    dvdy = -(w * U_t(c) * np.cos(w * x) + w * U_tt(c) * np.cos(2 * w * x))
+    J = jump - 2 * c.mu_b * (1 - c.mu_ratio) * dvdy
+    sig = surface_tension(c, sigma0, temperature(c, x, zero))
+    c0 = -np.mean(J / sig) / np.mean(1 / sig)
+    hpp = -(J + c0) / sig
+    k = 2 * np.pi * np.fft.rfftfreq(n, d=c.l / n)
+    H = np.fft.rfft(hpp)
+    H[1:] = -H[1:] / k[1:] ** 2
+    H[0] = 0.0
+    return x, np.fft.irfft(H, n)
+
+
 def U_s(c: Channel) -> float:
     """App. C, Eq. (U_s): characteristic thermocapillary velocity."""
     C1 = (c.T_h * (c.a / c.b) + c.T_c * c.k_ratio) / ((c.a / c.b) + c.k_ratio)
@@ -225,6 +283,21 @@ def interface_profile(ux: np.ndarray, phi: np.ndarray) -> np.ndarray:
         j = int(k[0])
         t = col[j] / (col[j] - col[j + 1])
         out[i] = (1 - t) * ux[j, i] + t * ux[j + 1, i]
+    return out
+
+
+def interface_height(phi: np.ndarray) -> np.ndarray:
+    """Row coordinate of the phi = 1/2 level in each column, linearly
+    interpolated between the two rows that bracket it (first crossing from
+    the bottom; NaN where there is none)."""
+    ny, nx = phi.shape
+    out = np.full(nx, np.nan)
+    for i in range(nx):
+        col = phi[:, i] - 0.5
+        k = np.nonzero((col[:-1] >= 0) & (col[1:] < 0))[0]
+        if k.size:
+            j = int(k[0])
+            out[i] = j + col[j] / (col[j] - col[j + 1])
     return out
 
 

@@ -130,6 +130,54 @@ def test_marangoni_stress_balance(c):
     assert np.max(np.abs(lhs - rhs)) < 1e-4 * scale
 
 
+@pytest.mark.parametrize("c", CH_BULK)
+def test_pressure_balances_the_viscous_force(c):
+    # Stokes momentum balance grad p = mu lap u in each layer: the pressure's
+    # closed form against second differences of the velocity field.
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, c.l, 40)
+    h = 2e-3 * min(c.a, c.b, c.l)
+    lap = lambda F, X, Y: (F(X + h, Y) + F(X - h, Y) + F(X, Y + h) + F(X, Y - h) - 4 * F(X, Y)) / h ** 2
+    U = lambda X, Y: an.velocity(c, X, Y)[0]
+    V = lambda X, Y: an.velocity(c, X, Y)[1]
+    P = lambda X, Y: an.pressure(c, X, Y)
+    for y, mu in ((rng.uniform(0.2 * c.a, 0.8 * c.a, 40), c.mu_b * c.mu_ratio),
+                  (-rng.uniform(0.2 * c.b, 0.8 * c.b, 40), c.mu_b)):
+        px, py = d_dx(P, x, y, h), d_dy(P, x, y, h)
+        scale = np.max(np.abs(px)) + np.max(np.abs(py))
+        assert np.max(np.abs(px - mu * lap(U, x, y))) < 1e-4 * scale
+        assert np.max(np.abs(py - mu * lap(V, x, y))) < 1e-4 * scale
+
+
+@pytest.mark.parametrize("c", CH_BULK)
+def test_small_deformation_balances_the_normal_stress(c):
+    # sigma(T) (-h'') must equal the jump of the normal stress -p + 2 mu dv/dy
+    # across the flat interface up to one constant; the jump is taken here
+    # from the pressure and from one-sided differences of v in each layer,
+    # h'' from second differences of the returned profile.
+    sigma0 = 1e-3
+    x, hgt = an.small_deformation(c, sigma0, n=4096)
+    dx = x[1] - x[0]
+    hpp = (np.roll(hgt, -1) - 2 * hgt + np.roll(hgt, 1)) / dx ** 2
+    e = 1e-5 * min(c.a, c.b)
+    V = lambda Y: an.velocity(c, x, np.full_like(x, Y))[1]
+    vya = (-3 * V(0.0) + 4 * V(e) - V(2 * e)) / (2 * e)
+    vyb = (3 * V(-1e-300) - 4 * V(-e) + V(-2 * e)) / (2 * e)
+    zero = np.zeros_like(x)
+    jump = (an.pressure(c, x, zero - 1e-300) - 2 * c.mu_b * vyb) \
+        - (an.pressure(c, x, zero) - 2 * c.mu_b * c.mu_ratio * vya)
+    sig = an.surface_tension(c, sigma0, an.temperature(c, x, zero))
+    assert np.min(sig) > 0
+    r = sig * (-hpp) - jump
+    assert np.std(r) <= 1e-4 * np.ptp(jump)        # zero jump for mirror-symmetric layers
+    assert abs(np.mean(hgt)) <= 1e-12 * np.ptp(hgt)
+    # the SRF channel of the deformation study: the interface rises under
+    # the hot spot, where sigma_TT (T - T_ref)^2 makes sigma largest
+    srf = an.Channel(a=75, b=25, l=200, mu_b=0.2, sigma_TT=3e-3)
+    x, hgt = an.small_deformation(srf, 1e-3, n=400)
+    assert np.argmax(hgt) == 0
+
+
 def test_nf_case_has_no_harmonic_and_srf_case_no_fundamental():
     nf = an.Channel(a=50, b=50, l=200, mu_b=0.1, sigma_T=-5e-4, sigma_TT=0.0)
     assert an.U_tt(nf) == 0.0 and an.U_t(nf) > 0
