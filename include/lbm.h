@@ -81,7 +81,8 @@ typedef void (*lbm_free_fn)(void* ptr, void* user);
 /* Create a context for n_inst independent channels (params[0..n_inst-1])
  * that are stepped together by single launches.  precision: lbm_precision.
  * hip_stream: the hipStream_t to order all work on (NULL: the null stream).  Rejects (LBM_EINVAL): n_inst <= 0,
- * nx or ny < 4, n_waves <= 0 or not dividing nx, W <= 0, b outside
+ * nx or ny < 4, nx * ny above 19 884 107 nodes (27 x 8 x nx x ny must stay below
+ * 2^32), n_waves <= 0 or not dividing nx, W <= 0, b outside
  * (W, ny - W), non-positive densities, viscosities, conductivities or
  * mobility.  On success *out owns all device memory of the context. */
 int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void* hip_stream,

@@ -49,6 +49,8 @@ struct lbm_ctx {
     float* tref_new = nullptr;         // references written by a check step
     int32_t* dl = nullptr;             // per-node phi-reference offsets, units of DL_Q (float32 mode)
     int32_t* dl_new = nullptr;         // offsets written by a check step
+    int32_t* dlz = nullptr;            // chunk flags of dl (nonzero offsets)
+    int max_chunks = 0;                // largest chunk count of one channel
     double* snap = nullptr;            // 4 * total_nodes
     double* partials = nullptr;        // n_tiles * 8 (capacity for the smallest tile)
     int partial_cap = 0;
@@ -134,7 +136,8 @@ int validate(const lbm_params& p) {
     const double vals[] = {p.sigma0, p.sigma_T, p.sigma_TT, p.T_ref, p.T_h, p.dT, p.T_c, p.Fx_ext, p.Fy_ext};
     for (double v : vals)
         if (!std::isfinite(v)) return LBM_EINVAL;
-    if ((long long)p.nx * p.ny > (1LL << 31) / 32) return LBM_EINVAL;
+    // populations are addressed by 32-bit byte offsets within a channel
+    if (27LL * 8LL * p.nx * p.ny >= (1LL << 32)) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -205,6 +208,7 @@ void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
     a.tref_out = c->tref_new;
     a.dl_v = c->dl;
     a.dl_out = c->dl_new;
+    a.dlz = c->dlz;
     for (int k = 0; k < 4; ++k) a.snap[k] = c->snap + (size_t)k * c->total_nodes;
     a.partials = c->partials;
     for (int k = 0; k < 5; ++k) a.out[k] = nullptr;
@@ -240,6 +244,8 @@ int enqueue_step(lbm_ctx* c, long long s) {
         r.dl_new = c->dl_new;
         hipError_t e = launch_tref_copy(r, c->max_nodes, c->n_inst, c->stream);
         if (e != hipSuccess) return fail_hip(c, e, "reference copy launch");
+        e = launch_dl_flags(c->d_inst, c->dl, c->dlz, c->max_chunks, c->n_inst, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "offset flag launch");
     }
     if (check) {
         FinArgs f;
@@ -337,7 +343,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->stream = (hipStream_t)hip_stream;
     // layout
     c->h_inst.resize(n_inst);
-    long long pop = 0, nodes = 0, rows = 0, cols = 0;
+    long long pop = 0, nodes = 0, rows = 0, cols = 0, chunks = 0;
     int min_tile_nodes = 16 * 16;  // smallest compiled tile: capacity for tile tables
     long long max_tiles = 0;
     for (int k = 0; k < n_inst; ++k) {
@@ -351,6 +357,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         I.node_off = nodes;
         I.row_off = rows;
         I.col_off = cols;
+        I.chunk_off = chunks;
         I.W = p.W;
         I.M_phi = p.M_phi;
         I.w_phi = 1.0 / (3.0 * p.M_phi + 0.5);
@@ -367,6 +374,11 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         nodes += n;
         rows += p.ny + 4;
         cols += p.nx;
+        {
+            const long long ch = (long long)((p.nx + DLZ_CX - 1) / DLZ_CX) * ((p.ny + DLZ_CY - 1) / DLZ_CY);
+            chunks += ch;
+            c->max_chunks = std::max<int>(c->max_chunks, (int)ch);
+        }
         c->max_nodes = std::max<long long>(c->max_nodes, n);
         // worst case over the compiled tile shapes (16 x 16 and 32 x 8 and 64 x 4 and 64 x 8)
         long long t = 0;
@@ -393,7 +405,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         c->tref_new = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
         c->dl = (int32_t*)dev_alloc(c, (size_t)nodes * sizeof(int32_t));
         c->dl_new = (int32_t*)dev_alloc(c, (size_t)nodes * sizeof(int32_t));
-        if (!c->tref || !c->tref_new || !c->dl || !c->dl_new) rc = LBM_ENOMEM;
+        c->dlz = (int32_t*)dev_alloc(c, (size_t)chunks * sizeof(int32_t));
+        if (!c->tref || !c->tref_new || !c->dl || !c->dl_new || !c->dlz) rc = LBM_ENOMEM;
     }
     c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
     c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
@@ -642,6 +655,10 @@ static int init_impl(lbm_ctx* c, const double* fields, bool device) {
     }
     hipError_t e = launch_init(c->prec, a, c->max_nodes, c->n_inst, c->stream);
     if (e != hipSuccess) return fail_hip(c, e, "init kernel launch");
+    if (c->prec == LBM_FP32_DEV) {
+        e = launch_dl_flags(c->d_inst, c->dl, c->dlz, c->max_chunks, c->n_inst, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "offset flag launch");
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (dfields) dev_release(c, dfields);
     c->steps = 0;

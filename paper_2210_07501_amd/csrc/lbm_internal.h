@@ -24,6 +24,10 @@ constexpr double EPS_N = 1e-6;
 // arithmetic) to the mass that writers removed.
 constexpr double DL_U = 1.0 / 268435456.0;   // 2^-28
 constexpr double DL_Q = 36.0 * DL_U;
+// Flag table over 64 x 8 node chunks: nonzero where any phi-reference offset
+// of the chunk is nonzero (float32 mode).  Lets a tile whose offsets are all
+// zero skip reading them and summing them.
+constexpr int DLZ_CX = 64, DLZ_CY = 8;
 
 // Per-channel descriptor in device memory.
 struct Inst {
@@ -33,6 +37,7 @@ struct Inst {
     long long node_off;           // element offset in node-sized arrays
     long long row_off;            // offset in the reference-row table (ny + 4 rows)
     long long col_off;            // offset in the bottom-wall temperature table (nx columns)
+    long long chunk_off;          // offset in the phi-offset flag table (ceil(nx/64) x ceil(ny/8) chunks)
     double W, M_phi, w_phi, b;
     double rho_a, rho_b, mu_a, mu_b, k_a, k_b;
     double s0, sT, sTT, T_ref;
@@ -62,6 +67,7 @@ struct StepArgs {
     void* tref_out;               // new references written by a check step
     const int32_t* dl_v;          // per-node phi-reference offset from phi0(row), in units of DL_Q (float32 mode)
     int32_t* dl_out;              // new offsets written by a check step
+    const int32_t* dlz;           // chunk flags of dl_v
     double* snap[4];              // ux, uy, T, phi at the last check
     double* partials;             // [tile][8]
     double* out[5];               // fields: phi, ux, uy, T, p
@@ -116,5 +122,7 @@ hipError_t launch_count_active(const Inst* insts, int n, int* out, hipStream_t s
 hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, hipStream_t st);
 hipError_t launch_state(int prec, const StateArgs& a, int nodes, hipStream_t st);
 hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStream_t st);
+hipError_t launch_dl_flags(const Inst* insts, const int32_t* dl, int32_t* dlz, int max_chunks, int n_inst,
+                           hipStream_t st);
 
 }  // namespace lbm
