@@ -115,7 +115,9 @@ def time_to_steady(n=16, cap=400_000):
     """Time to residual 1e-8 on n held-out warm-start channels (256 x 128,
     seeds 900000 + i): plain float64 solves from rest, one channel at a time,
     against one batched float32-deviation solve started from the trained
-    network's prediction (inference included) and one from rest."""
+    network's prediction (inference included) and one from rest.  Float32
+    channels whose residual levels off above the tolerance are finished in
+    float64 within the same step cap (warmstart.solve_batch)."""
     import numpy as np
     import torch
 

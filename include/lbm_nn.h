@@ -113,18 +113,24 @@ int nn_cast_weights(const float* w, uint16_t* w16, uint16_t* wflip, int32_t co, 
 int nn_features(const lbm_params* params, int32_t n, uint16_t* x, int32_t cpad, void* stream);
 
 /* Network output pred [n][ny][nx][4] float32 (u / U_s, v / U_s,
- * (T - T_ref) / dT, phi) -> fields [n][phi | ux | uy | T][ny][nx] float64
- * in the layout lbm_init_device reads.  phi_from_net != 0: phi is the
- * network's output clipped to [0, 1]; 0: the cold-start tanh profile (the
- * conservative Allen-Cahn equation removes a bulk error in phi only by
- * diffusion at mobility M_phi, far slower than u and T relax, and it keeps
- * sum phi, so the hand-off keeps the exact initial interface).
- * Synchronises. */
+ * (T - T_ref) / dT, 50 (phi - phi_cold) on the interface band) -> fields
+ * [n][phi | ux | uy | T][ny][nx] float64 in the layout lbm_init_device
+ * reads.  phi_cold is the cold-start tanh profile (width W at y = b - 1/2);
+ * the band is |y - (b - 1/2)| <= 3 W.  phi_from_net == 0: phi = phi_cold.
+ * phi_from_net != 0: phi = phi_cold + the predicted deviation on the band,
+ * plus a rigid shift of the interface (proportional to d phi_cold / dy)
+ * that makes sum phi equal the cold start's -- the conservative Allen-Cahn
+ * equation keeps sum phi, so the warm and cold starts reach the same steady
+ * state.  Phi outside the band is exactly phi_cold (a bulk error there
+ * would decay only by diffusion at mobility M_phi).  Synchronises. */
 int nn_to_fields(const lbm_params* params, int32_t n, const float* pred, double* fields, int32_t phi_from_net,
                  void* stream);
 
-/* Inverse map: fields [n][phi | ux | uy | T][ny][nx] float64 -> training
- * targets [n][ny][nx][4] float32.  Synchronises. */
+/* Training targets from converged fields: fields [n][phi | ux | uy | T]
+ * [ny][nx] float64 -> target [n][ny][nx][4] float32 (u / U_s, v / U_s,
+ * (T - T_ref) / dT, 50 (phi - phi_cold) on the interface band and 0
+ * outside).  nn_to_fields inverts it up to float32 rounding and, for phi,
+ * the sum-restoring shift.  Synchronises. */
 int nn_targets(const lbm_params* params, int32_t n, const double* fields, float* target, void* stream);
 
 /* Velocity scale U_s of the network outputs for one channel:

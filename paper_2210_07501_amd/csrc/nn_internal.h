@@ -8,6 +8,11 @@ namespace nn {
 
 constexpr int MAX_CH = 96;               // widest layer (channels, padded to 32)
 constexpr int NFEAT = 10;                // input planes
+// The network's fourth output is the deviation of phi from the cold-start
+// tanh profile, times PHI_DEV_SCALE, on the interface band |y - (b - 1/2)|
+// <= PHI_BAND W (zero outside).  Steady deviations are a few 1e-3 to 1e-1.
+constexpr double PHI_DEV_SCALE = 50.0;
+constexpr double PHI_BAND = 3.0;
 
 // Per-channel description for the feature and hand-off kernels.
 struct ChanDesc {

@@ -423,28 +423,54 @@ __global__ __launch_bounds__(256) void features_kernel(const ChanDesc* desc, uin
 // pred[n][y][x][4] (u / U_s, v / U_s, (T - T_ref) / dT, phi) -> LBM init fields
 // [n][phi | ux | uy | T][y][x] in float64.  phi: the network's, clipped to
 // [0, 1] (phi_net != 0), or the cold-start tanh profile.
-__global__ __launch_bounds__(256) void to_fields_kernel(const ChanDesc* desc, const float* pred, double* fields, int n, int h, int w,
+__device__ __forceinline__ bool in_band(const ChanDesc& d, int j) {
+    return fabs((double)j - (d.b - 0.5)) <= PHI_BAND * d.W;
+}
+// shape of a rigid shift of the cold-start interface (proportional to its
+// y-derivative)
+__device__ __forceinline__ double shift_shape(const ChanDesc& d, int j) {
+    const double c = cosh(2.0 * ((d.b - 0.5) - (double)j) / d.W);
+    return 1.0 / (c * c);
+}
+
+// One block per channel.  phi: the cold-start profile, plus (phi_net) the
+// predicted deviation on the interface band and the rigid interface shift
+// that returns sum phi to the cold start's (sum over the band of the
+// deviation, S, cancelled by -S / (w sum_j g(j)) g(j)).
+__global__ __launch_bounds__(256) void to_fields_kernel(const ChanDesc* desc, const float* pred, double* fields, int h, int w,
                                                         int phi_net) {
-    const long long total = (long long)n * h * w;
-    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= total) return;
-    const long long hw = (long long)h * w;
-    const int b = (int)(k / hw);
-    const long long q = k - b * hw;
+    __shared__ double red[256];
+    const int b = blockIdx.x;
     const ChanDesc& d = desc[b];
-    const float* p = pred + (size_t)k * 4;
-    double ph;
-    if (phi_net) {
-        ph = (double)p[3];
-        ph = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
-    } else {
-        ph = phi_tanh(d, (int)(q / w));
-    }
+    const long long hw = (long long)h * w;
+    const float* P = pred + (size_t)b * hw * 4;
     double* o = fields + (size_t)b * 4 * hw;
-    o[q] = ph;
-    o[hw + q] = (double)p[0] * d.U_s;
-    o[2 * hw + q] = (double)p[1] * d.U_s;
-    o[3 * hw + q] = d.T_ref + d.dT * (double)p[2];
+    double corr = 0.0;
+    if (phi_net) {
+        double s = 0.0;
+        for (long long q = threadIdx.x; q < hw; q += 256)
+            if (in_band(d, (int)(q / w))) s += (double)P[q * 4 + 3];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        double G = 0.0;
+        for (int j = 0; j < h; ++j)
+            if (in_band(d, j)) G += shift_shape(d, j);
+        corr = G > 0.0 ? -(red[0] / PHI_DEV_SCALE) / (G * (double)w) : 0.0;
+    }
+    for (long long q = threadIdx.x; q < hw; q += 256) {
+        const int j = (int)(q / w);
+        const float* p = P + q * 4;
+        double ph = phi_tanh(d, j);
+        if (phi_net && in_band(d, j)) ph += (double)p[3] / PHI_DEV_SCALE + corr * shift_shape(d, j);
+        o[q] = ph;
+        o[hw + q] = (double)p[0] * d.U_s;
+        o[2 * hw + q] = (double)p[1] * d.U_s;
+        o[3 * hw + q] = d.T_ref + d.dT * (double)p[2];
+    }
 }
 
 // converged LBM fields [n][phi | ux | uy | T][y][x] float64 -> targets [n][y][x][4] float32
@@ -461,7 +487,8 @@ __global__ __launch_bounds__(256) void targets_kernel(const ChanDesc* desc, cons
     o[0] = (float)(f[hw + q] / d.U_s);
     o[1] = (float)(f[2 * hw + q] / d.U_s);
     o[2] = (float)((f[3 * hw + q] - d.T_ref) / d.dT);
-    o[3] = (float)f[q];
+    const int j = (int)(q / w);
+    o[3] = in_band(d, j) ? (float)((f[q] - phi_tanh(d, j)) * PHI_DEV_SCALE) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -552,7 +579,8 @@ hipError_t launch_features(const ChanDesc* d, uint16_t* x, int n, int h, int w, 
 
 hipError_t launch_to_fields(const ChanDesc* d, const float* pred, double* fields, int n, int h, int w, int phi_net,
                             hipStream_t st) {
-    to_fields_kernel<<<blocks_of((long long)n * h * w), 256, 0, st>>>(d, pred, fields, n, h, w, phi_net);
+    if (n <= 0) return hipSuccess;
+    to_fields_kernel<<<(unsigned)n, 256, 0, st>>>(d, pred, fields, h, w, phi_net);
     return hipGetLastError();
 }
 

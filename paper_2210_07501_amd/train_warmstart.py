@@ -80,7 +80,7 @@ def cmd_evaluate(a):
     # warm, whole held-out set
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pred = net.predict_fields(cfgs)
+    pred = net.predict_fields(cfgs, phi_from_net=a.phi == "net")
     torch.cuda.synchronize()
     t_nn = time.perf_counter() - t0
     ctx_w, wall_w, res_w = ws.solve_batch(cfgs, lbm.LBM_FP32_DEV, cap=a.cap, init_fields=pred)
@@ -91,7 +91,7 @@ def cmd_evaluate(a):
     ref = ws.fields_tensor(ctx_c, len(cfgs))
     lbm.lbm_destroy(ctx_c)
     log("evaluate: cold batch %.1f s" % wall_c)
-    err = ws.relative_errors(pred, ref)
+    err = ws.relative_errors(pred, ref, phi0=ws.cold_phi(cfgs))
     # cold single float64 on a subset, and warm on the same subset
     sub = cfgs[:a.n_single]
     t_single, steps_single = 0.0, []
@@ -103,7 +103,7 @@ def cmd_evaluate(a):
         log("evaluate: single float64 %d/%d: %d steps, %.2f s" % (k + 1, len(sub), res[0]["steps"], wall))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pred_s = net.predict_fields(sub)
+    pred_s = net.predict_fields(sub, phi_from_net=a.phi == "net")
     torch.cuda.synchronize()
     t_nn_s = time.perf_counter() - t0
     ctx, wall_ws, res_ws = ws.solve_batch(sub, lbm.LBM_FP32_DEV, cap=a.cap, init_fields=pred_s, verbose=False)
@@ -119,7 +119,7 @@ def cmd_evaluate(a):
 
     sw, sc = np.array([r["steps"] for r in res_w]), np.array([r["steps"] for r in res_c])
     out = dict(
-        n_eval=len(cfgs), cap=a.cap,
+        n_eval=len(cfgs), cap=a.cap, phi=a.phi,
         warm_batch=dict(wall_s=round(wall_w + t_nn, 2), inference_s=round(t_nn, 3), **stats(res_w)),
         cold_batch=dict(wall_s=round(wall_c, 2), **stats(res_c)),
         step_ratio_cold_over_warm_median=float(np.median(sc / np.maximum(sw, 1))),
@@ -151,6 +151,8 @@ def main():
     e.add_argument("--n-eval", type=int, default=256)
     e.add_argument("--n-single", type=int, default=16)
     e.add_argument("--cap", type=int, default=400_000)
+    e.add_argument("--phi", choices=("net", "cold"), default="net",
+                   help="hand-off phi: cold-start profile plus the predicted deviation, or the profile alone")
     a = ap.parse_args()
     lbm.load()
     {"train": cmd_train, "evaluate": cmd_evaluate}[a.cmd](a)

@@ -257,9 +257,11 @@ class WarmStartNet:
         nn.nn_features(cfgs, x, CPAD)
         return x
 
-    def predict_fields(self, cfgs, batch: int = 32, phi_from_net: bool = False):
-        """Device float64 fields [n][phi|ux|uy|T][ny][nx] for lbm_init_device
-        (phi: the cold-start profile unless phi_from_net)."""
+    def predict_fields(self, cfgs, batch: int = 32, phi_from_net: bool = True):
+        """Device float64 fields [n][phi|ux|uy|T][ny][nx] for lbm_init_device.
+        phi: the cold-start profile plus the network's deviation on the
+        interface band, shifted to keep sum phi (phi_from_net), or the
+        cold-start profile alone."""
         t = self.torch
         ny, nx = int(cfgs[0]["ny"]), int(cfgs[0]["nx"])
         out = t.empty((len(cfgs), 4, ny, nx), dtype=t.float64, device=self.dev)
@@ -279,12 +281,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_fields=None, tile=None, verbose=True):
+def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_fields=None, tile=None, verbose=True,
+                finish_fp64=True):
     """Batched solve to r <= tol (each channel retires on convergence).
-    Returns (ctx, wall seconds, per-channel residual records)."""
+    Returns (ctx, wall seconds, per-channel residual records).
+
+    Float32 contexts: on weakly driven channels the float32 residual can
+    level off just above the tolerance (rounding of the capillary and
+    Marangoni forces).  With finish_fp64, a channel whose residual is below
+    1e-6 but has not halved over the last 100 000 steps counts as stalled;
+    once only stalled channels remain active, their states move into a
+    float64 context (lbm_get_state / lbm_set_state, exact) which finishes
+    them, and the result is written back.  Their records then hold the
+    float64 residual, the total steps and "finished_fp64": True."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    n = len(cfgs)
     ctx = lbm.lbm_create(cfgs, precision=precision)
     if tile:
         lbm.lbm_set_tile(ctx, *tile)
@@ -292,18 +305,45 @@ def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_field
         lbm.lbm_init(ctx)
     else:
         lbm.lbm_init_device(ctx, init_fields)
+    watch = finish_fp64 and precision == lbm.LBM_FP32_DEV
+    back = max(1, -(-100_000 // chunk))         # chunks in 100 000 steps
+    hist = []
+    stalled = set()
     done = 0
     while done < cap:
         step = min(chunk, cap - done)
         rc, active = lbm.lbm_solve(ctx, tol, step)
         done += step
         if verbose:
-            log("  solve: %d steps, %d of %d active, %.1f s" % (done, active, len(cfgs), time.perf_counter() - t0))
+            log("  solve: %d steps, %d of %d active, %.1f s" % (done, active, n, time.perf_counter() - t0))
         if active == 0:
             break
+        if watch:
+            res = [lbm.lbm_residual(ctx, k) for k in range(n)]
+            hist.append([r["r"] for r in res])
+            live = [k for k in range(n) if res[k]["r"] > tol]
+            if len(hist) > back:
+                stalled = {k for k in live if hist[-1][k] < 1e-6 and hist[-1][k] > 0.5 * hist[-1 - back][k]}
+                if live and all(k in stalled for k in live):
+                    break
+    res = [lbm.lbm_residual(ctx, k) for k in range(n)]
+    todo = [k for k in range(n) if watch and res[k]["r"] > tol]
+    if todo and done < cap:
+        if verbose:
+            log("  solve: finishing %d channel(s) in float64 after %d steps" % (len(todo), done))
+        c64 = lbm.lbm_create([cfgs[k] for k in todo], precision=lbm.LBM_FP64)
+        for q, k in enumerate(todo):
+            lbm.lbm_set_state(c64, q, lbm.lbm_get_state(ctx, k))
+        lbm.lbm_solve(c64, tol, cap - done)
+        for q, k in enumerate(todo):
+            r64 = lbm.lbm_residual(c64, q)
+            lbm.lbm_set_state(ctx, k, lbm.lbm_get_state(c64, q))
+            r64["steps"] = res[k]["steps"] + r64["steps"]
+            r64["finished_fp64"] = True
+            res[k] = r64
+        lbm.lbm_destroy(c64)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    res = [lbm.lbm_residual(ctx, k) for k in range(len(cfgs))]
     return ctx, wall, res
 
 
@@ -350,9 +390,22 @@ def train(net, X, Y, epochs, batch=16, lr=2e-3, lr_min=2e-5, warmup=100, seed=0,
     return hist
 
 
-def relative_errors(pred, ref, T_ref=1.0):
+def cold_phi(cfgs):
+    """Cold-start phi profile of each channel, [n][ny][nx] float64 on the GPU."""
+    import torch
+    out = []
+    for c in cfgs:
+        j = torch.arange(int(c["ny"]), dtype=torch.float64, device="cuda")
+        ph = 0.5 * (1 + torch.tanh(2 * ((c["b"] - 0.5) - j) / c["W"]))
+        out.append(ph[:, None].expand(int(c["ny"]), int(c["nx"])))
+    return torch.stack(out)
+
+
+def relative_errors(pred, ref, T_ref=1.0, phi0=None):
     """Per-output relative L2 errors of [n][4][ny][nx] fields (phi, ux, uy, T):
-    phi, and T - T_ref, relative to their own norms; u, v relative to |u|."""
+    T - T_ref relative to its own norm; u, v relative to |u|; phi relative to
+    the norm of its deviation from phi0 (the cold-start profile) when given,
+    else to its own norm."""
     import torch
     out = {}
     names = ("phi", "ux", "uy", "T")
@@ -363,6 +416,8 @@ def relative_errors(pred, ref, T_ref=1.0):
             den = unorm
         elif name == "T":
             den = torch.sqrt(torch.sum((ref[:, 3] - T_ref) ** 2, dim=(1, 2)))
+        elif phi0 is not None:
+            den = torch.sqrt(torch.sum((ref[:, 0] - phi0) ** 2, dim=(1, 2)))
         else:
             den = torch.sqrt(torch.sum(ref[:, 0] ** 2, dim=(1, 2)))
         out[name] = (d / den).cpu().numpy()

@@ -153,8 +153,10 @@ def test_mse_and_adam(env):
 
 
 def test_features_targets_and_handoff(env):
-    """Input planes against their definitions; targets and the hand-off to the
-    LBM are inverse maps; lbm_init_device equals lbm_init from host fields."""
+    """Input planes against their definitions; targets against their
+    definitions (phi: the scaled deviation from the cold-start profile on the
+    interface band); the hand-off inverts them, keeps sum phi and the bulk
+    phi exact; lbm_init_device equals lbm_init from host fields."""
     torch, nn = env
     from paper_2210_07501_amd import lbm
     cfgs = inputs.warmstart_set(3, 900_000)
@@ -183,25 +185,40 @@ def test_features_targets_and_handoff(env):
     Fd = torch.from_numpy(F).cuda()
     tgt = torch.empty((3, ny, nx, 4), dtype=torch.float32, device="cuda")
     nn.nn_targets(cfgs, Fd, tgt)
+    T = tgt.cpu().numpy()
     back = torch.empty_like(Fd)
     nn.nn_to_fields(cfgs, tgt, back, phi_from_net=True)
-    # the targets are float32: each field comes back to float32 rounding of its scale
     Bk = back.cpu().numpy()
-    for c in range(4):
+    # default hand-off: the cold-start phi profile, the network's u, v, T
+    cold = torch.empty_like(Fd)
+    nn.nn_to_fields(cfgs, tgt, cold)
+    Ch = cold.cpu().numpy()
+    # u, v, T: the targets are float32, each field comes back to float32 rounding of its scale
+    for c in (1, 2, 3):
         ref = F[:, c] - (1.0 if c == 3 else 0.0)
         assert np.max(np.abs(Bk[:, c] - F[:, c])) <= 2e-7 * np.max(np.abs(ref)), c
     for k, c in enumerate(cfgs):
         us = nn.nn_velocity_scale(c)
         assert us == pytest.approx(0.01 * (abs(c["sigma_T"]) + c["sigma_TT"]) / c["mu_b"], rel=1e-12)
-        assert np.allclose(tgt.cpu().numpy()[k, :, :, 0], F[k, 1] / us, rtol=1e-6, atol=1e-6)
-    # default hand-off: the cold-start phi profile, the network's u, v, T
-    cold = torch.empty_like(Fd)
-    nn.nn_to_fields(cfgs, tgt, cold)
-    Ch = cold.cpu().numpy()
+        assert np.allclose(T[k, :, :, 0], F[k, 1] / us, rtol=1e-6, atol=1e-6)
+        # phi: 50 (phi - phi_cold) on the band |y - (b - 1/2)| <= 3 W, zero outside
+        j = np.arange(ny)
+        zeta = (c["b"] - 0.5) - j
+        ph = 0.5 * (1 + np.tanh(2 * zeta / c["W"]))
+        band = np.abs(zeta) <= 3 * c["W"]
+        dev = (F[k, 0] - ph[:, None]) * band[:, None]
+        assert np.allclose(T[k, :, :, 3], 50 * dev, rtol=0, atol=5e-6)
+        # hand-off: phi_cold + deviation + the rigid shift that restores sum phi
+        g = np.where(band, 1 / np.cosh(2 * zeta / c["W"]) ** 2, 0.0)
+        S = np.sum(T[k, :, :, 3].astype(np.float64)) / 50
+        expect = ph[:, None] + T[k, :, :, 3].astype(np.float64) / 50 - S / (nx * g.sum()) * g[:, None]
+        assert np.max(np.abs(Bk[k, 0] - expect)) < 1e-12
+        assert np.array_equal(Bk[k, 0][~band], Ch[k, 0][~band])    # bulk phi untouched
+        assert Bk[k, 0].sum() == pytest.approx(Ch[k, 0].sum(), rel=1e-12)
     for k, c in enumerate(cfgs):
         ph = 0.5 * (1 + np.tanh(2 * ((c["b"] - 0.5) - np.arange(ny)) / c["W"]))
         assert np.allclose(Ch[k, 0], np.broadcast_to(ph[:, None], (ny, nx)), rtol=0, atol=1e-15)
-        assert np.array_equal(Ch[k, 1:], back.cpu().numpy()[k, 1:])
+        assert np.array_equal(Ch[k, 1:], Bk[k, 1:])
     for prec in (0, 1):
         a = lbm.lbm_create(cfgs, precision=prec)
         b = lbm.lbm_create(cfgs, precision=prec)

@@ -2,15 +2,17 @@
 900000 + i, 256 x 128), measured against the method without it.
 
 Batched float32 solves to residual 1e-8 are started once from the network's
-prediction (u, v, T from the network, phi the cold-start profile) and once
-from rest.  Checked: the network's raw error is far below that of the state
-at rest; both starts converge for the same channels and end in the same
-steady state; the warm start needs no more steps in total than the cold one
-(within 5%).  The step saving itself is printed, not asserted: with a
-residual criterion on the relative change per 100 steps, the last decades
-of convergence are set by the slowest viscous and thermal modes, which a
-few-percent prediction error barely shortens (measured: about 3% fewer
-steps at the median, per-channel ratios 0.8 - 1.5).
+prediction and once from rest.  The hand-off takes u, v, T from the network
+and phi as the cold-start profile plus the network's deviation on the
+interface band, shifted so that sum phi is the cold start's; channels
+whose float32 residual levels off above the tolerance are finished in
+float64.  Checked: the network's raw errors are far below those of the
+state at rest; every channel converges from both starts and ends in the
+same steady state; it needs at least 10% fewer steps in total over the channels both
+converge on (measured on 256 held-out channels: median 92 501 against
+120 751 steps, per-channel median ratio 1.26).  The remaining steps are set
+by the slow viscous, thermal and interface modes, which a prediction a few
+percent off shortens only logarithmically.
 """
 import os
 
@@ -23,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "paper_2210_07501_amd", "weights", "warmstart.npz")
-N = 8
+N = 16
 CAP = 600_000
 
 
@@ -50,27 +52,31 @@ def test_warm_start_saves_steps_and_reaches_the_same_state(env):
     sw = np.array([r["steps"] for r in res_w])
     sc = np.array([r["steps"] for r in res_c])
     print("steps warm", sw.tolist(), "cold", sc.tolist(), "wall warm %.2f cold %.2f s" % (wall_w, wall_c), flush=True)
-    conv_w = [r["r"] <= 1e-8 for r in res_w]
-    conv_c = [r["r"] <= 1e-8 for r in res_c]
-    assert conv_w == conv_c
-    assert sw.sum() <= 1.05 * sc.sum()
-    print("cold / warm steps: total %.3f, per channel %s" % (sc.sum() / sw.sum(), np.round(sc / sw, 2).tolist()),
-          flush=True)
+    conv_w = np.array([r["r"] <= 1e-8 for r in res_w])
+    conv_c = np.array([r["r"] <= 1e-8 for r in res_c])
+    # stalled float32 channels are finished in float64: every channel converges
+    assert conv_w.all() and conv_c.all()
+    both = conv_w & conv_c
+    print("cold / warm steps: total %.3f, per channel %s" % (sc[both].sum() / sw[both].sum(),
+          np.round(sc / sw, 2).tolist()), flush=True)
+    assert sw[both].sum() <= 0.9 * sc[both].sum()
     Fw = ws.fields_tensor(ctx_w, N)
     Fc = ws.fields_tensor(ctx_c, N)
     err = ws.relative_errors(Fw, Fc)
-    raw = ws.relative_errors(pred, Fc)
-    # the state at rest (u = 0, T linear between the walls) as a "prediction"
+    phi0 = ws.cold_phi(cfgs)
+    raw = ws.relative_errors(pred, Fc, phi0=phi0)
+    # the state at rest (u = 0, T linear between the walls, the cold phi) as a "prediction"
     ctx0 = lbm.lbm_create(cfgs, precision=lbm.LBM_FP64)
     lbm.lbm_init(ctx0)
-    rest = ws.relative_errors(ws.fields_tensor(ctx0, N), Fc)
+    rest = ws.relative_errors(ws.fields_tensor(ctx0, N), Fc, phi0=phi0)
     print("network raw error (median)", {k: float(np.median(v)) for k, v in raw.items()},
           "state at rest", {k: float(np.median(v)) for k, v in rest.items()},
           "warm vs cold steady state (max)", {k: float(np.max(v)) for k, v in err.items()}, flush=True)
     assert np.median(raw["T"]) < 0.5 * np.median(rest["T"])
     assert np.median(raw["ux"]) < 0.25 and np.median(raw["uy"]) < 0.25    # rest: 1
+    assert np.median(raw["phi"]) < 0.5                                       # rest: 1
     for k, c in enumerate(cfgs):
-        if conv_w[k]:
+        if both[k]:
             # both stopped at r <= 1e-8: the same steady state to the
             # convergence level of the residual
             assert err["ux"][k] < 1e-2 and err["uy"][k] < 1e-2 and err["T"][k] < 1e-3 and err["phi"][k] < 1e-3
