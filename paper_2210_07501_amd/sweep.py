@@ -7,8 +7,10 @@ Channels follow the batched-sweep distribution (inputs.batched_sweep): nx in
 {128, 256, 512}, ny = nx / 2, s1, s2, layer fraction and property ratios
 drawn from the seed.  The tile shape is chosen by lbm_autotune on the full
 batch; the step loop runs as hipGraph replays of 100 steps with device-side
-retirement (lbm_solve).  Prints one JSON line: wall time, converged count,
-steps per channel (median, max, by size) and the effective update rate.
+retirement (lbm_solve).  Float32 channels whose residual levels off just above
+the tolerance are finished in float64 (warmstart.run_to_tolerance; --no-finish
+turns this off).  Prints one JSON line: wall time, converged count, steps per
+channel (median, max, by size) and the effective update rate.
 """
 from __future__ import annotations
 
@@ -19,7 +21,7 @@ import time
 
 import numpy as np
 
-from . import inputs, lbm
+from . import inputs, lbm, warmstart as ws
 
 
 def log(*a):
@@ -33,6 +35,8 @@ def main():
     ap.add_argument("--cap", type=int, default=3_000_000)
     ap.add_argument("--chunk", type=int, default=100_000)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--no-finish", action="store_true",
+                    help="do not finish stalled float32 channels in float64")
     a = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -46,16 +50,9 @@ def main():
         % (len(cfgs), nodes, dev_bytes / 1e9, tx, ty, ms))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    active = len(cfgs)
-    while done < a.cap and active > 0:
-        step = min(a.chunk, a.cap - done)
-        rc, active = lbm.lbm_solve(ctx, 1e-8, step)
-        done += step
-        log("sweep: %d steps, %d of %d active, %.1f s" % (done, active, len(cfgs), time.perf_counter() - t0))
+    res = ws.run_to_tolerance(ctx, cfgs, prec, 1e-8, a.cap, a.chunk, True, not a.no_finish, t0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    res = [lbm.lbm_residual(ctx, k) for k in range(len(cfgs))]
     steps = np.array([r["steps"] for r in res])
     conv = np.array([r["r"] <= 1e-8 for r in res])
     sizes = np.array([c["nx"] * c["ny"] for c in cfgs])
@@ -66,6 +63,7 @@ def main():
         by_size[str(nx)] = dict(channels=int(m.sum()), converged=int(conv[m].sum()),
                                 median_steps=int(np.median(steps[m])), max_steps=int(steps[m].max()))
     out = dict(channels=len(cfgs), nodes=int(nodes), precision=a.precision, tile=[tx, ty],
+               finished_fp64=int(sum(bool(r.get("finished_fp64")) for r in res)),
                tile_ms_full_batch=round(ms, 4), cap=a.cap, wall_s=round(wall, 1), converged=int(conv.sum()),
                median_steps=int(np.median(steps)), max_steps=int(steps.max()), by_nx=by_size,
                node_updates=updates, effective_glups=round(updates / wall / 1e9, 2),

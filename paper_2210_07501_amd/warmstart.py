@@ -281,10 +281,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_fields=None, tile=None, verbose=True,
-                finish_fp64=True):
-    """Batched solve to r <= tol (each channel retires on convergence).
-    Returns (ctx, wall seconds, per-channel residual records).
+def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, verbose=True, finish_fp64=True,
+                     t0=None):
+    """Step an initialised context until every channel has r <= tol or the
+    cap; returns the per-channel residual records.
 
     Float32 contexts: on weakly driven channels the float32 residual can
     level off just above the tolerance (rounding of the capillary and
@@ -292,23 +292,14 @@ def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_field
     1e-6 but has not halved over the last 100 000 steps counts as stalled;
     once only stalled channels remain active, their states move into a
     float64 context (lbm_get_state / lbm_set_state, exact) which finishes
-    them, and the result is written back.  Their records then hold the
-    float64 residual, the total steps and "finished_fp64": True."""
-    import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    them within the remaining cap, and the result is written back.  Their
+    records then hold the float64 residual, the total steps and
+    "finished_fp64": True."""
+    t0 = time.perf_counter() if t0 is None else t0
     n = len(cfgs)
-    ctx = lbm.lbm_create(cfgs, precision=precision)
-    if tile:
-        lbm.lbm_set_tile(ctx, *tile)
-    if init_fields is None:
-        lbm.lbm_init(ctx)
-    else:
-        lbm.lbm_init_device(ctx, init_fields)
     watch = finish_fp64 and precision == lbm.LBM_FP32_DEV
     back = max(1, -(-100_000 // chunk))         # chunks in 100 000 steps
     hist = []
-    stalled = set()
     done = 0
     while done < cap:
         step = min(chunk, cap - done)
@@ -342,6 +333,25 @@ def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_field
             r64["finished_fp64"] = True
             res[k] = r64
         lbm.lbm_destroy(c64)
+    return res
+
+
+def solve_batch(cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, init_fields=None, tile=None, verbose=True,
+                finish_fp64=True):
+    """Batched solve to r <= tol (each channel retires on convergence), with
+    the float64 finish of run_to_tolerance.  Returns (ctx, wall seconds,
+    per-channel residual records)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = lbm.lbm_create(cfgs, precision=precision)
+    if tile:
+        lbm.lbm_set_tile(ctx, *tile)
+    if init_fields is None:
+        lbm.lbm_init(ctx)
+    else:
+        lbm.lbm_init_device(ctx, init_fields)
+    res = run_to_tolerance(ctx, cfgs, precision, tol, cap, chunk, verbose, finish_fp64, t0)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return ctx, wall, res
