@@ -129,6 +129,12 @@ int lbm_fields(lbm_ctx* ctx, int32_t inst, double* phi, double* ux, double* uy, 
 int lbm_residual(lbm_ctx* ctx, int32_t inst, double* r, double* sum_phi, double* sum_mass,
                  double* u_int_peak, int64_t* steps_done);
 
+/* Retire instance inst now, as if it had converged at the current step:
+ * later steps and solves leave it untouched, and lbm_residual reports its
+ * last check.  Its state stays readable (and writable through
+ * lbm_set_state).  No effect on a retired instance.  Synchronises. */
+int lbm_retire(lbm_ctx* ctx, int32_t inst);
+
 /* Raw populations of instance inst, float64 [3][9][ny][nx] (host).  Syncs. */
 int lbm_get_state(lbm_ctx* ctx, int32_t inst, double* pop);
 /* Overwrite instance inst with populations (host, float64 [3][9][ny][nx]). */

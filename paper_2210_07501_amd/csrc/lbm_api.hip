@@ -15,6 +15,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <cstddef>
 
 #include "../../include/lbm.h"
 #include "lbm_internal.h"
@@ -740,6 +741,28 @@ int lbm_solve(lbm_ctx* c, double r_tol, int64_t max_steps, int32_t* n_active) {
     }
     if (n_active) *n_active = act;
     return bad ? LBM_EDIVERGED : LBM_OK;
+}
+
+int lbm_retire(lbm_ctx* c, int32_t inst) {
+    if (!c || inst < 0 || inst >= c->n_inst) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    std::vector<Result> res;
+    int rc = refresh_results(c, res);
+    if (rc) return rc;
+    if (res[inst].retired_at > 0) return LBM_OK;          // already retired
+    // the channel keeps the state of the current step: record it as retired
+    // there, switch its descriptor off and drop its tiles from the launches
+    Result R = res[inst];
+    R.retired_at = c->steps;
+    const int off = 0;
+    HIPCHK(c, hipMemcpyAsync(c->d_res + inst, &R, sizeof(Result), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char*)(c->d_inst + inst) + offsetof(Inst, active), &off, sizeof(int),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->retired[inst] = 1;
+    rc = build_tiles(c, false);
+    if (rc) return rc;
+    return upload_tables(c);
 }
 
 int lbm_fields(lbm_ctx* c, int32_t inst, double* phi, double* ux, double* uy, double* T, double* p) {

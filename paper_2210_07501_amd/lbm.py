@@ -21,7 +21,8 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 
 # Every function declared in include/lbm.h.
 EXPORTS = ("lbm_create", "lbm_init", "lbm_init_device", "lbm_step", "lbm_solve", "lbm_fields", "lbm_residual",
-           "lbm_get_state", "lbm_set_state", "lbm_profile_steps", "lbm_set_tile", "lbm_autotune", "lbm_info",
+           "lbm_get_state", "lbm_set_state", "lbm_retire", "lbm_profile_steps", "lbm_set_tile", "lbm_autotune",
+           "lbm_info",
            "lbm_destroy", "lbm_strerror")
 
 
@@ -77,6 +78,7 @@ def load():
     L.lbm_set_state.argtypes = [vp, ctypes.c_int32, dp]
     L.lbm_profile_steps.argtypes = [vp, ctypes.c_int64, dp]
     L.lbm_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.lbm_retire.argtypes = [vp, ctypes.c_int32]
     L.lbm_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                dp]
     L.lbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -269,6 +271,10 @@ def lbm_profile_steps(ctx: _Ctx, n: int) -> float:
     ms = ctypes.c_double()
     _check(load().lbm_profile_steps(ctx.h, int(n), ctypes.byref(ms)), "lbm_profile_steps")
     return ms.value
+
+
+def lbm_retire(ctx: _Ctx, inst: int):
+    _check(load().lbm_retire(ctx.h, int(inst)), "lbm_retire")
 
 
 def lbm_set_tile(ctx: _Ctx, tx: int, ty: int):

@@ -58,13 +58,17 @@ def cmd_train(a):
     Y = torch.empty((len(cfgs), ny, nx, 4), dtype=torch.float32, device="cuda")
     nn.nn_targets(cfgs, F, Y)
     del F
+    # train on steady states only: a channel stopped by the cap is not one
+    keep = torch.tensor(np.nonzero(conv)[0], dtype=torch.long, device="cuda")
+    X, Y = X[keep].contiguous(), Y[keep].contiguous()
+    log("train: %d converged channels as training data" % X.shape[0])
     log("train: target rms per output", [float(v) for v in torch.sqrt(torch.mean(Y ** 2, dim=(0, 1, 2))).cpu()])
     t0 = time.perf_counter()
     hist = ws.train(net, X, Y, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=a.seed, time_limit=a.time_limit)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     net.save(a.out)
-    out = dict(n_train=len(cfgs), data_wall_s=round(wall, 1), data_converged=int(conv.sum()),
+    out = dict(n_train=len(cfgs), n_used=int(X.shape[0]), data_wall_s=round(wall, 1), data_converged=int(conv.sum()),
                data_median_steps=int(np.median(steps)), data_max_steps=int(steps.max()), cap=a.cap,
                epochs=len(hist), train_s=round(t_train, 1), loss_first=hist[0], loss_last=hist[-1],
                params=ws.n_params(), weights=a.out)

@@ -290,17 +290,35 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
     level off just above the tolerance (rounding of the capillary and
     Marangoni forces).  With finish_fp64, a channel whose residual is below
     1e-6 but has not halved over the last 100 000 steps counts as stalled;
-    once only stalled channels remain active, their states move into a
-    float64 context (lbm_get_state / lbm_set_state, exact) which finishes
-    them within the remaining cap, and the result is written back.  Their
-    records then hold the float64 residual, the total steps and
+    stalled channels move at once into a float64 context (lbm_get_state /
+    lbm_set_state, exact), which finishes them within the remaining cap, and
+    are retired from the float32 context with the finished state written
+    back.  Their records then hold the float64 residual, the total steps and
     "finished_fp64": True."""
     t0 = time.perf_counter() if t0 is None else t0
     n = len(cfgs)
     watch = finish_fp64 and precision == lbm.LBM_FP32_DEV
     back = max(1, -(-100_000 // chunk))         # chunks in 100 000 steps
     hist = []
+    finished = {}
     done = 0
+
+    def finish(todo, fp32_steps):
+        if verbose:
+            log("  solve: finishing %d channel(s) in float64 after %d steps" % (len(todo), done))
+        c64 = lbm.lbm_create([cfgs[k] for k in todo], precision=lbm.LBM_FP64)
+        for q, k in enumerate(todo):
+            lbm.lbm_set_state(c64, q, lbm.lbm_get_state(ctx, k))
+        lbm.lbm_solve(c64, tol, cap - done)
+        for q, k in enumerate(todo):
+            r64 = lbm.lbm_residual(c64, q)
+            lbm.lbm_set_state(ctx, k, lbm.lbm_get_state(c64, q))
+            lbm.lbm_retire(ctx, k)
+            r64["steps"] = fp32_steps[k] + r64["steps"]
+            r64["finished_fp64"] = True
+            finished[k] = r64
+        lbm.lbm_destroy(c64)
+
     while done < cap:
         step = min(chunk, cap - done)
         rc, active = lbm.lbm_solve(ctx, tol, step)
@@ -312,27 +330,14 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
         if watch:
             res = [lbm.lbm_residual(ctx, k) for k in range(n)]
             hist.append([r["r"] for r in res])
-            live = [k for k in range(n) if res[k]["r"] > tol]
-            if len(hist) > back:
-                stalled = {k for k in live if hist[-1][k] < 1e-6 and hist[-1][k] > 0.5 * hist[-1 - back][k]}
-                if live and all(k in stalled for k in live):
-                    break
+            live = [k for k in range(n) if res[k]["r"] > tol and k not in finished]
+            if len(hist) > back and done < cap:
+                stalled = [k for k in live if hist[-1][k] < 1e-6 and hist[-1][k] > 0.5 * hist[-1 - back][k]]
+                if stalled:
+                    finish(stalled, {k: res[k]["steps"] for k in stalled})
     res = [lbm.lbm_residual(ctx, k) for k in range(n)]
-    todo = [k for k in range(n) if watch and res[k]["r"] > tol]
-    if todo and done < cap:
-        if verbose:
-            log("  solve: finishing %d channel(s) in float64 after %d steps" % (len(todo), done))
-        c64 = lbm.lbm_create([cfgs[k] for k in todo], precision=lbm.LBM_FP64)
-        for q, k in enumerate(todo):
-            lbm.lbm_set_state(c64, q, lbm.lbm_get_state(ctx, k))
-        lbm.lbm_solve(c64, tol, cap - done)
-        for q, k in enumerate(todo):
-            r64 = lbm.lbm_residual(c64, q)
-            lbm.lbm_set_state(ctx, k, lbm.lbm_get_state(c64, q))
-            r64["steps"] = res[k]["steps"] + r64["steps"]
-            r64["finished_fp64"] = True
-            res[k] = r64
-        lbm.lbm_destroy(c64)
+    for k, r in finished.items():
+        res[k] = r
     return res
 
 

@@ -96,3 +96,29 @@ def test_autotune_leaves_state_and_picks_a_supported_shape(lbm, prec):
         for d in range(3):
             # float32: the halo and own-node sums round differently per shape
             assert np.max(np.abs(x[d] - y[d])) <= (1e-12 if prec == 0 else 1e-6) * np.max(np.abs(y[d]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_retire_on_request(lbm, prec):
+    """lbm_retire stops one channel at the current step: its state and step
+    count stay as they were while the rest of the batch goes on, and the
+    rest match their single-channel runs bitwise."""
+    cfgs = channels()[:2]
+    print("case: retire on request, precision", prec, flush=True)
+    ctx = lbm.lbm_create(cfgs, precision=prec)
+    lbm.lbm_init(ctx)
+    lbm.lbm_step(ctx, 250)
+    held = lbm.lbm_get_state(ctx, 0)
+    lbm.lbm_retire(ctx, 0)
+    lbm.lbm_retire(ctx, 0)                     # a second call changes nothing
+    rc, active = lbm.lbm_solve(ctx, 1e-300, 300)
+    assert active == 1
+    lbm.lbm_step(ctx, 50)
+    assert np.array_equal(lbm.lbm_get_state(ctx, 0), held)
+    assert lbm.lbm_residual(ctx, 0)["steps"] == 250
+    n1 = lbm.lbm_residual(ctx, 1)["steps"]       # lbm_solve stops at a check boundary
+    assert n1 >= 500
+    one = lbm.lbm_create([cfgs[1]], precision=prec)
+    lbm.lbm_init(one)
+    lbm.lbm_step(one, n1)
+    assert np.array_equal(lbm.lbm_get_state(ctx, 1), lbm.lbm_get_state(one, 0))
