@@ -63,6 +63,8 @@ def _create(cfg, n_inst=1, prec=0):
     dict(nx=2), dict(ny=3), dict(n_waves=3), dict(n_waves=0), dict(W=0.0), dict(b=3.0),
     dict(b=62.0), dict(M_phi=0.0), dict(mu_a=-0.1), dict(k_b=0.0), dict(rho_a=0.0),
     dict(sigma_T=float("nan")), dict(T_h=float("inf")),
+    # channel size: 27 x 8 x nx x ny must stay below 2^32 (4096 x 4864 is just over)
+    dict(nx=4096, ny=4864, b=2432.0),
 ])
 def test_create_rejects_invalid_parameters(bad):
     cfg = inputs.small_channel()
@@ -81,6 +83,7 @@ def test_create_rejects_bad_arguments():
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert L.lbm_init(None, None) == lbm.LBM_EINVAL
     assert L.lbm_set_tile(None, 32, 8) == lbm.LBM_EINVAL
+    assert L.lbm_retire(None, 0) == lbm.LBM_EINVAL
 
 
 def test_strerror():
