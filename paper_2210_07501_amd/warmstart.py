@@ -289,7 +289,9 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
     Float32 contexts: on weakly driven channels the float32 residual can
     level off just above the tolerance (rounding of the capillary and
     Marangoni forces).  With finish_fp64, a channel whose residual is below
-    1e-6 but has not halved over the last 100 000 steps counts as stalled;
+    1e-7 but has fallen less than fourfold over the last 100 000 steps
+    counts as stalled (a float32 floor, or a decay too slow to be worth
+    waiting for in float32);
     stalled channels move at once into a float64 context (lbm_get_state /
     lbm_set_state, exact), which finishes them within the remaining cap, and
     are retired from the float32 context with the finished state written
@@ -332,7 +334,7 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
             hist.append([r["r"] for r in res])
             live = [k for k in range(n) if res[k]["r"] > tol and k not in finished]
             if len(hist) > back and done < cap:
-                stalled = [k for k in live if hist[-1][k] < 1e-6 and hist[-1][k] > 0.5 * hist[-1 - back][k]]
+                stalled = [k for k in live if hist[-1][k] < 1e-7 and hist[-1][k] > 0.25 * hist[-1 - back][k]]
                 if stalled:
                     finish(stalled, {k: res[k]["steps"] for k in stalled})
     res = [lbm.lbm_residual(ctx, k) for k in range(n)]
