@@ -132,7 +132,8 @@ int lbm_residual(lbm_ctx* ctx, int32_t inst, double* r, double* sum_phi, double*
 /* Retire instance inst now, as if it had converged at the current step:
  * later steps and solves leave it untouched, and lbm_residual reports its
  * last check.  Its state stays readable (and writable through
- * lbm_set_state).  No effect on a retired instance.  Synchronises. */
+ * lbm_set_state).  No effect on a retired instance.  LBM_ESTATE before
+ * the first step after init.  Synchronises. */
 int lbm_retire(lbm_ctx* ctx, int32_t inst);
 
 /* Raw populations of instance inst, float64 [3][9][ny][nx] (host).  Syncs. */

@@ -745,7 +745,8 @@ int lbm_solve(lbm_ctx* c, double r_tol, int64_t max_steps, int32_t* n_active) {
 
 int lbm_retire(lbm_ctx* c, int32_t inst) {
     if (!c || inst < 0 || inst >= c->n_inst) return LBM_EINVAL;
-    if (!c->initialised) return LBM_ESTATE;
+    // a retirement step of 0 would read as "not retired"
+    if (!c->initialised || c->steps == 0) return LBM_ESTATE;
     std::vector<Result> res;
     int rc = refresh_results(c, res);
     if (rc) return rc;

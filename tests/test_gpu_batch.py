@@ -107,6 +107,9 @@ def test_retire_on_request(lbm, prec):
     print("case: retire on request, precision", prec, flush=True)
     ctx = lbm.lbm_create(cfgs, precision=prec)
     lbm.lbm_init(ctx)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_retire(ctx, 0)                 # before the first step
+    assert e.value.status == lbm.LBM_ESTATE
     lbm.lbm_step(ctx, 250)
     held = lbm.lbm_get_state(ctx, 0)
     lbm.lbm_retire(ctx, 0)
