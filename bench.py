@@ -84,12 +84,14 @@ def cpu_baseline(target_s=12.0, target_1=6.0):
     def rate(target):
         o = orc.Oracle(cfg)
         o.init_cold()
+        o.step(10)                                   # thread start-up, caches
         t = time.perf_counter()
         o.step(10)
-        est = (time.perf_counter() - t) / 10
-        n = max(10, int(target / max(est, 1e-6)))
-        t = time.perf_counter()
-        o.step(n)
+        chunk = max(10, int(1.0 / max((time.perf_counter() - t) / 10, 1e-6)))   # about 1 s
+        n, t = 0, time.perf_counter()
+        while time.perf_counter() - t < target:      # timed in chunks until the target is reached
+            o.step(chunk)
+            n += chunk
         dt = time.perf_counter() - t
         return nodes * n / dt / 1e6, n, dt
 
