@@ -9,7 +9,8 @@ of the peak interface velocity):
   u <= 1e-5 of the peak interface velocity after 2000 steps of the small
   channel (measured 8.0e-6; the step is deterministic, so the figure
   reproduces exactly for a given build);
-  sum phi drifts by < 1e-8 relative over 2000 steps."""
+  sum phi drifts by < 1e-8 relative over 2000 steps;
+  the same population bars at the full 4096 x 2048 size after 3 steps."""
 import numpy as np
 import pytest
 
@@ -120,3 +121,16 @@ def test_phi_conservation_fp32(lbm):
     lbm.lbm_step(ctx, 2000)
     r1 = lbm.lbm_residual(ctx)
     assert abs(r1["sum_phi"] - r0["sum_phi"]) / r0["sum_phi"] < 1e-8
+
+
+def test_full_size_throughput_channel_fp32(lbm):
+    """4096 x 2048, 8 wavelengths, in the launch configuration of the
+    benchmark (64 x 8 tiles; a check step then two every-step launches):
+    float32 storage against the float64 oracle on every node."""
+    cfg = inputs.throughput_channel()
+    print("case: 4096x2048 float32, 3 steps", flush=True)
+    ctx = run32(lbm, cfg, 3)
+    pop = lbm.lbm_get_state(ctx)
+    del ctx
+    errs = check_pops(pop, run_oracle(cfg, 3).pop)
+    print("float32 full-size population errors", errs, flush=True)
