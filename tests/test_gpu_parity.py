@@ -202,3 +202,16 @@ def test_full_size_throughput_channel(lbm):
     del ctx
     o = run_oracle(cfg, 3)
     compare_state(pop, o.pop)
+
+
+def test_largest_channel_below_the_size_limit(lbm):
+    """4096 x 4800 (19.7 M nodes): population byte offsets reach 4.25e9,
+    just below the 2^32 the 32-bit addressing allows.  A check step and an
+    every-step launch against the oracle, every node."""
+    cfg = dict(inputs.throughput_channel(), ny=4800, b=1440.0)
+    assert 27 * 8 * cfg["nx"] * cfg["ny"] < 2 ** 32 < 27 * 8 * cfg["nx"] * (cfg["ny"] + 64)
+    print("case: 4096x4800 float64, 2 steps", flush=True)
+    ctx = gpu_run(lbm, cfg, 2)
+    pop = lbm.lbm_get_state(ctx)
+    del ctx
+    compare_state(pop, run_oracle(cfg, 2).pop)
