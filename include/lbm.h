@@ -158,7 +158,9 @@ int lbm_set_tile(lbm_ctx* ctx, int32_t tx, int32_t ty);
  * per launch in ms.  Synchronises. */
 int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* tx, int32_t* ty, double* ms);
 
-/* Number of lattice nodes over all instances, and device bytes held. */
+/* Number of lattice nodes over all instances, and the device bytes the
+ * context holds: every live allocation (through the caller's allocator when
+ * one was given), rounded up to 256 bytes each. */
 int lbm_info(lbm_ctx* ctx, int64_t* nodes, int64_t* device_bytes);
 
 void lbm_destroy(lbm_ctx* ctx);

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 #include <cstddef>
 
@@ -63,8 +64,8 @@ struct lbm_ctx {
     double* d_tol = nullptr;
     int* d_active = nullptr;
     int* h_active = nullptr;           // pinned
-    std::vector<void*> allocations;
-    size_t device_bytes = 0;
+    std::vector<std::pair<void*, size_t>> allocations;   // live device allocations and their sizes
+    size_t device_bytes = 0;                             // sum of their sizes
     // state
     bool initialised = false;
     long long steps = 0;               // steps of the channels still active
@@ -103,25 +104,42 @@ void* dev_alloc(lbm_ctx* c, size_t bytes) {
         if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
     }
     if (p) {
-        c->allocations.push_back(p);
+        c->allocations.emplace_back(p, bytes);
         c->device_bytes += bytes;
     }
     return p;
 }
 
-// Free one temporary allocation made by dev_alloc.
+// Two timing events, destroyed on every return path.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t create() {
+        hipError_t e = hipEventCreate(&e0);
+        return e == hipSuccess ? hipEventCreate(&e1) : e;
+    }
+    ~EventPair() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// Free one temporary allocation made by dev_alloc.  Calls that fail after
+// making a temporary leave it in the context's list, to be freed by
+// lbm_destroy: work already queued on the stream may still use it.
 void dev_release(lbm_ctx* c, void* p) {
-    auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+    auto it = std::find_if(c->allocations.begin(), c->allocations.end(),
+                           [p](const std::pair<void*, size_t>& a) { return a.first == p; });
     if (it == c->allocations.end()) return;
+    c->device_bytes -= it->second;
     c->allocations.erase(it);
     if (c->free_fn) c->free_fn(p, c->user);
     else (void)hipFree(p);
 }
 
 void dev_free_all(lbm_ctx* c) {
-    for (void* p : c->allocations) {
-        if (c->free_fn) c->free_fn(p, c->user);
-        else (void)hipFree(p);
+    for (auto& a : c->allocations) {
+        if (c->free_fn) c->free_fn(a.first, c->user);
+        else (void)hipFree(a.first);
     }
     c->allocations.clear();
     c->device_bytes = 0;
@@ -345,7 +363,6 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     // layout
     c->h_inst.resize(n_inst);
     long long pop = 0, nodes = 0, rows = 0, cols = 0, chunks = 0;
-    int min_tile_nodes = 16 * 16;  // smallest compiled tile: capacity for tile tables
     long long max_tiles = 0;
     for (int k = 0; k < n_inst; ++k) {
         const lbm_params& p = params[k];
@@ -381,12 +398,11 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
             c->max_chunks = std::max<int>(c->max_chunks, (int)ch);
         }
         c->max_nodes = std::max<long long>(c->max_nodes, n);
-        // worst case over the compiled tile shapes (16 x 16 and 32 x 8 and 64 x 4 and 64 x 8)
+        // tile-table capacity: the worst case over the compiled tile shapes
         long long t = 0;
         for (auto& s : TILE_SHAPES) t = std::max<long long>(t, (long long)tiles_of(p, s[0], s[1], nullptr));
         max_tiles += t;
     }
-    (void)min_tile_nodes;
     c->total_pop = pop;
     c->total_nodes = nodes;
     c->total_rows = rows;
@@ -538,10 +554,20 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
                 }
             }
         }
+        // every set-up copy goes on the context's stream (which the caller
+        // may have created non-blocking) and completes before its host
+        // source goes out of scope
         auto upload = [&](void* dst, const std::vector<double>& v) -> hipError_t {
-            if (precision == LBM_FP64) return hipMemcpy(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
-            std::vector<float> f(v.begin(), v.end());
-            return hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+            hipError_t e;
+            if (precision == LBM_FP64) {
+                e = hipMemcpyAsync(dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            } else {
+                std::vector<float> f(v.begin(), v.end());
+                e = hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+            return e;
         };
         if (upload(c->phi0, t0) != hipSuccess || upload(c->phir, tr) != hipSuccess || upload(c->fq, tq) != hipSuccess ||
             upload(c->fr, tf) != hipSuccess)
@@ -558,25 +584,28 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         }
         hipError_t e;
         if (precision == LBM_FP64) {
-            e = hipMemcpy(c->twall, td.data(), cols * sizeof(double), hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(c->twall, td.data(), cols * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         } else {
             std::vector<float> tf(td.begin(), td.end());
-            e = hipMemcpy(c->twall, tf.data(), cols * sizeof(float), hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(c->twall, tf.data(), cols * sizeof(float), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         }
         if (e != hipSuccess) rc = fail_hip(c, e, "upload wall temperatures");
     }
     if (rc == LBM_OK) rc = build_tiles(c, true);
     if (rc == LBM_OK) {
-        if (hipMemcpy(c->d_inst, c->h_inst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->d_tile_inst, c->h_tile_inst.data(), sizeof(int) * c->n_tiles, hipMemcpyHostToDevice) !=
+        const double tol = -1.0;
+        if (hipMemcpyAsync(c->d_inst, c->h_inst.data(), sizeof(Inst) * n_inst, hipMemcpyHostToDevice, c->stream) !=
                 hipSuccess ||
-            hipMemset(c->d_res, 0, sizeof(Result) * n_inst) != hipSuccess ||
-            hipMemset(c->d_counter, 0, sizeof(long long)) != hipSuccess) {
+            hipMemcpyAsync(c->d_tile_inst, c->h_tile_inst.data(), sizeof(int) * c->n_tiles, hipMemcpyHostToDevice,
+                           c->stream) != hipSuccess ||
+            hipMemsetAsync(c->d_res, 0, sizeof(Result) * n_inst, c->stream) != hipSuccess ||
+            hipMemsetAsync(c->d_counter, 0, sizeof(long long), c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->d_tol, &tol, sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
             rc = fail_hip(c, hipErrorUnknown, "upload descriptors");
         }
-        double tol = -1.0;
-        if (rc == LBM_OK && hipMemcpy(c->d_tol, &tol, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-            rc = fail_hip(c, hipErrorUnknown, "upload tolerance");
     }
     if (rc != LBM_OK) {
         lbm_destroy(c);
@@ -602,9 +631,7 @@ int lbm_set_tile(lbm_ctx* c, int32_t tx, int32_t ty) {
     bool ok = false;
     for (auto& s : TILE_SHAPES) ok = ok || (s[0] == tx && s[1] == ty);
     if (!ok) return LBM_EINVAL;
-    if (c->initialised && (c->steps % 2) != 0) {
-        // the tile shape may change at any step; buffers are unaffected
-    }
+    // the tile shape may change at any step: the buffers do not depend on it
     c->tx = tx;
     c->ty = ty;
     int rc = build_tiles(c, !c->initialised);
@@ -875,9 +902,9 @@ int lbm_set_state(lbm_ctx* c, int32_t inst, const double* pop) {
 int lbm_profile_steps(lbm_ctx* c, int64_t n, double* ms) {
     if (!c || n <= 0 || !ms) return LBM_EINVAL;
     if (!c->initialised) return LBM_ESTATE;
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    EventPair ev;
+    HIPCHK(c, ev.create());
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int64_t k = 0; k < n; ++k) {
         StepArgs a;
@@ -890,13 +917,12 @@ int lbm_profile_steps(lbm_ctx* c, int64_t n, double* ms) {
     HIPCHK(c, hipEventSynchronize(e1));
     float t = 0.f;
     HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     *ms = (double)t / (double)n;
     // profiled steps record no checks: move the check counter to the step
     // index of the next check so that later checks report their own step
     long long next = ((c->steps + CHECK_EVERY - 1) / CHECK_EVERY) * CHECK_EVERY;
-    HIPCHK(c, hipMemcpy(c->d_counter, &next, sizeof(long long), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpyAsync(c->d_counter, &next, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
@@ -904,9 +930,9 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tx_out, int32_t* ty_out, dou
     if (!c || reps <= 0) return LBM_EINVAL;
     if (!c->initialised) return LBM_ESTATE;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    EventPair ev;
+    HIPCHK(c, ev.create());
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     int best = -1;
     double best_ms = 0.0;
     const int tx0 = c->tx, ty0 = c->ty;
@@ -933,8 +959,6 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tx_out, int32_t* ty_out, dou
         const double ms = (double)t / reps;
         if (best < 0 || ms < best_ms) { best = s; best_ms = ms; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc) {
         (void)lbm_set_tile(c, tx0, ty0);
         return rc;
@@ -950,12 +974,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tx_out, int32_t* ty_out, dou
 int lbm_info(lbm_ctx* c, int64_t* nodes, int64_t* device_bytes) {
     if (!c) return LBM_EINVAL;
     if (nodes) *nodes = c->total_nodes;
-    if (device_bytes) {
-        size_t b = 0;
-        b += 2 * (size_t)c->total_pop * c->elem;
-        b += (size_t)c->total_nodes * 4 * sizeof(double);
-        *device_bytes = (int64_t)b;
-    }
+    if (device_bytes) *device_bytes = (int64_t)c->device_bytes;
     return LBM_OK;
 }
 

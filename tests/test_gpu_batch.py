@@ -125,3 +125,54 @@ def test_retire_on_request(lbm, prec):
     lbm.lbm_init(one)
     lbm.lbm_step(one, n1)
     assert np.array_equal(lbm.lbm_get_state(ctx, 1), lbm.lbm_get_state(one, 0))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_info_counts_the_device_bytes_held(lbm, prec):
+    """lbm_info: every live allocation of the context, which at least holds
+    the two population buffers and the float64 residual snapshot; the
+    temporaries of lbm_fields, lbm_get_state and lbm_set_state are released."""
+    cs = channels()
+    nodes = sum(c["nx"] * c["ny"] for c in cs)
+    elem = 8 if prec == 0 else 4
+    ctx = lbm.lbm_create(cs, precision=prec)
+    lbm.lbm_init(ctx)
+    n, b0 = lbm.lbm_info(ctx)
+    print("nodes", n, "device bytes", b0, "per node %.1f" % (b0 / n), flush=True)
+    assert n == nodes
+    floor = (2 * 27 * elem + 4 * 8) * nodes
+    per_node_tables = 0 if prec == 0 else 16          # float32: T references and phi offsets, twice
+    assert floor <= b0 <= floor + per_node_tables * nodes + (1 << 20)
+    lbm.lbm_step(ctx, 10)
+    lbm.lbm_fields(ctx, 2)
+    pop = lbm.lbm_get_state(ctx, 1)
+    lbm.lbm_set_state(ctx, 1, pop)
+    assert lbm.lbm_info(ctx) == (n, b0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_profiled_steps_advance_the_state_like_plain_steps(lbm, prec):
+    """lbm_profile_steps launches plain steps only (no checks).  In float64 a
+    check step writes the same populations as a plain one, so 150 profiled
+    steps equal 150 stepped ones bit for bit; in float32 the skipped checks
+    keep the old storage references, which changes the rounding only.  The
+    checks that follow report their own step index."""
+    cs = channels()
+    a = lbm.lbm_create(cs, precision=prec)
+    lbm.lbm_init(a)
+    ms = lbm.lbm_profile_steps(a, 150)
+    assert ms > 0
+    b = lbm.lbm_create(cs, precision=prec)
+    lbm.lbm_init(b)
+    lbm.lbm_step(b, 150)
+    for k in range(len(cs)):
+        pa, pb = lbm.lbm_get_state(a, k), lbm.lbm_get_state(b, k)
+        if prec == 0:
+            assert np.array_equal(pa, pb), k
+        else:
+            for d in range(3):
+                scale = np.max(np.abs(pb[d]))
+                assert np.max(np.abs(pa[d] - pb[d])) <= 1e-6 * scale, (k, d)
+    lbm.lbm_step(a, 151)
+    r = lbm.lbm_residual(a, 0)
+    assert r["steps"] == 301 and not r["diverged"] and np.isfinite(r["r"])
