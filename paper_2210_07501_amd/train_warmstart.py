@@ -59,9 +59,10 @@ def cmd_train(a):
     nn.nn_targets(cfgs, F, Y)
     del F
     # train on steady states only: a channel stopped by the cap is not one
-    keep = torch.tensor(np.nonzero(conv)[0], dtype=torch.long, device="cuda")
+    # (--keep-unconverged: every channel, for short timing runs)
+    keep = torch.tensor(np.nonzero(conv | a.keep_unconverged)[0], dtype=torch.long, device="cuda")
     X, Y = X[keep].contiguous(), Y[keep].contiguous()
-    log("train: %d converged channels as training data" % X.shape[0])
+    log("train: %d channels as training data" % X.shape[0])
     log("train: target rms per output", [float(v) for v in torch.sqrt(torch.mean(Y ** 2, dim=(0, 1, 2))).cpu()])
     t0 = time.perf_counter()
     hist = ws.train(net, X, Y, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=a.seed, time_limit=a.time_limit)
@@ -150,6 +151,8 @@ def main():
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--time-limit", type=float, default=None)
     t.add_argument("--out", required=True)
+    t.add_argument("--keep-unconverged", action="store_true",
+                   help="train on every generated channel, also those stopped by the cap (timing runs)")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", required=True)
     e.add_argument("--n-eval", type=int, default=256)

@@ -379,6 +379,8 @@ def train(net, X, Y, epochs, batch=16, lr=2e-3, lr_min=2e-5, warmup=100, seed=0,
     import torch
     N, h, w = X.shape[0], X.shape[1], X.shape[2]
     steps_per_epoch = N // batch
+    if steps_per_epoch == 0:
+        raise ValueError("training needs at least one batch: %d samples, batch %d" % (N, batch))
     total = epochs * steps_per_epoch
     g = torch.Generator(device="cpu").manual_seed(seed)
     hist = []

@@ -59,6 +59,26 @@ def test_conv_forward(env, ci, co, relu):
     assert np.all(np.abs(host(y16) - ref) <= 2.0 ** -8 * np.abs(ref) + 2e-5 * scale)
 
 
+@pytest.mark.parametrize("n,h,w,ci,co", [
+    (1, 3, 256, 64, 32),    # one row per work-group (LDS-staged path)
+    (3, 2, 128, 32, 96),    # two rows per work-group, each group straddles two images
+    (1, 5, 64, 96, 64),     # four rows per work-group, ragged: the last group has one row
+    (2, 3, 192, 32, 32),    # a width outside 64 / 128 / 256: the unstaged path
+])
+def test_conv_forward_row_widths(env, n, h, w, ci, co):
+    """Every launch shape of the forward convolution, periodic in x and
+    zero-padded in y, against the oracle."""
+    torch, nn = env
+    rng = np.random.default_rng(n * h * w + ci + co)
+    x, xr = bf(torch, rng.normal(size=(n, h, w, ci)))
+    wt, wr = bf(torch, rng.normal(size=(co, 9, ci)) / np.sqrt(9 * ci))
+    b = rng.normal(size=co).astype(np.float32)
+    y32 = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    nn.nn_conv3x3_fwd(x, wt, f32(torch, b), None, y32, co, n, h, w, ci, co, 0)
+    ref = O.conv3x3(xr, wr, b.astype(np.float64))
+    assert np.max(np.abs(host(y32) - ref)) <= 2e-5 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("ci,co", [(32, 32), (64, 96), (96, 64)])
 def test_conv_backward(env, ci, co):
     torch, nn = env

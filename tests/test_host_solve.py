@@ -121,3 +121,14 @@ def test_nothing_is_finished_past_the_cap(monkeypatch):
 def test_float64_contexts_are_not_finished_again(monkeypatch):
     fake, ctx, res = run(["floor"], 400_000, prec=FakeLBM.LBM_FP64, monkeypatch=monkeypatch)
     assert not any(c[0] in ("retire", "get") for c in fake.calls)
+
+
+def test_training_refuses_an_empty_set():
+    """No converged channel (or fewer than one batch): a clear error before
+    any network call, not a division by zero after the first epoch."""
+    import torch
+    from paper_2210_07501_amd import warmstart as ws
+    X = torch.empty((3, 4, 64, 32), dtype=torch.bfloat16)
+    Y = torch.empty((3, 4, 64, 4))
+    with pytest.raises(ValueError, match="at least one batch"):
+        ws.train(None, X, Y, epochs=1, batch=16)
