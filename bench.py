@@ -215,11 +215,15 @@ def main():
                 "kernel_ms": round(r["kernel_ms"], 4), "bytes_per_update": bpu}
 
     if lbm.LBM_FP64 not in out or lbm.LBM_FP32_DEV not in out:
-        # partial runs (profiling) print the per-precision numbers only
+        # partial runs (profiling, tile sweeps) print the per-precision numbers only
+        names = {lbm.LBM_FP64: "fp64", lbm.LBM_FP32_DEV: "fp32_dev"}
+        part = {"partial": True, "tile": args.tile or "default"}
         for prec, r in out.items():
-            log("bench: precision %d: %.1f MLUPS, kernel %.4f ms" % (
-                prec, r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6, r["kernel_ms"]))
-        print(json.dumps({str(p): roof(p) for p in out}), flush=True)
+            mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
+            log("bench: precision %d: %.1f MLUPS, kernel %.4f ms" % (prec, mlups, r["kernel_ms"]))
+            part[names[prec]] = {"value": round(mlups, 1), "unit": "MLUPS",
+                                 "ms_per_step": round(r["ms_total"] / args.steps, 4), "roofline": roof(prec)}
+        print(json.dumps(part), flush=True)
         return
     r64 = out[lbm.LBM_FP64]
     mlups64 = r64["nodes"] * args.steps / (r64["ms_total"] * 1e-3) / 1e6
