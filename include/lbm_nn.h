@@ -70,13 +70,15 @@ int nn_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dx, int64_t cou
 int nn_add(const uint16_t* a, const uint16_t* b, uint16_t* out, int64_t count, void* stream);
 
 /* 2x2 average pooling between [n][h][wd][c] and [n][h/2][wd/2][c] (h, wd
- * even).  backward = 0: in is the fine tensor, out the coarse one;
+ * even, c a multiple of 8, buffers 16-byte aligned; n h and wd c below
+ * 2^31).  backward = 0: in is the fine tensor, out the coarse one;
  * backward = 1: in is the coarse gradient, out the fine gradient. */
 int nn_pool2(int32_t backward, const uint16_t* in, uint16_t* out, int32_t n, int32_t h, int32_t wd, int32_t c,
              void* stream);
 
 /* Nearest-neighbour x2 upsampling between [n][h][wd][c] (coarse) and
- * [n][2h][2wd][c].  backward = 0: coarse -> fine; backward = 1: fine
+ * [n][2h][2wd][c] (c a multiple of 8, buffers 16-byte aligned; 2 n h and
+ * 2 wd c below 2^31).  backward = 0: coarse -> fine; backward = 1: fine
  * gradient -> coarse gradient (sum of the four children). */
 int nn_up2(int32_t backward, const uint16_t* in, uint16_t* out, int32_t n, int32_t h, int32_t wd, int32_t c,
            void* stream);

@@ -143,13 +143,15 @@ int nn_add(const uint16_t* a, const uint16_t* b, uint16_t* out, int64_t count, v
 
 int nn_pool2(int32_t backward, const uint16_t* in, uint16_t* out, int32_t n, int32_t h, int32_t wd, int32_t c,
              void* stream) {
-    if (!in || !out || n <= 0 || h <= 0 || wd <= 0 || c <= 0 || h % 2 || wd % 2) return LBM_EINVAL;
+    if (!in || !out || n <= 0 || h <= 0 || wd <= 0 || c <= 0 || c % 8 || h % 2 || wd % 2) return LBM_EINVAL;
+    if ((long long)n * h >= (1LL << 31) || (long long)wd * c >= (1LL << 31)) return LBM_EINVAL;
     return status(launch_pool(backward ? 1 : 0, in, out, n, h, wd, c, S(stream)));
 }
 
 int nn_up2(int32_t backward, const uint16_t* in, uint16_t* out, int32_t n, int32_t h, int32_t wd, int32_t c,
            void* stream) {
-    if (!in || !out || n <= 0 || h <= 0 || wd <= 0 || c <= 0) return LBM_EINVAL;
+    if (!in || !out || n <= 0 || h <= 0 || wd <= 0 || c <= 0 || c % 8) return LBM_EINVAL;
+    if ((long long)n * 2 * h >= (1LL << 31) || (long long)2 * wd * c >= (1LL << 31)) return LBM_EINVAL;
     return status(launch_up(backward ? 1 : 0, in, out, n, h, wd, c, S(stream)));
 }
 

@@ -10,6 +10,7 @@
 // channel is periodic), zero padding in y (walls).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "nn_internal.h"
@@ -357,62 +358,122 @@ __global__ __launch_bounds__(256) void add_kernel(const uint16_t* a, const uint1
     if (k < n) o[k] = f2b(b2f(a[k]) + b2f(b[k]));
 }
 
-// 2x2 average pooling; (h, w) are the input sizes.
+// Pooling and upsampling move 8 channels (16 bytes) per thread; c is a
+// multiple of 8.  blockIdx.y walks output rows (image b, row i), so the
+// per-thread index arithmetic is 32-bit and small.  Arithmetic per channel
+// is unchanged: the pooled value is 0.25 (x00 + x01 + x10 + x11) in float.
+__device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *(const uint4*)p; }
+__device__ __forceinline__ void st16(uint16_t* p, uint4 v) { *(uint4*)p = v; }
+__device__ __forceinline__ float lo_f(uint32_t v) { return __uint_as_float(v << 16); }
+__device__ __forceinline__ float hi_f(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
+__device__ __forceinline__ uint32_t pk(float lo, float hi) { return (uint32_t)f2b(lo) | ((uint32_t)f2b(hi) << 16); }
+
+// average pool 2x2: x [n][h][w][c] -> y [n][h/2][w/2][c]
 __global__ __launch_bounds__(256) void pool_fwd_kernel(const uint16_t* x, uint16_t* y, int n, int h, int w, int c) {
-    const long long total = (long long)n * (h / 2) * (w / 2) * c;
-    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= total) return;
-    const int ch = (int)(k % c);
-    long long q = k / c;
-    const int j = (int)(q % (w / 2));
-    q /= (w / 2);
-    const int i = (int)(q % (h / 2));
-    const int b = (int)(q / (h / 2));
-    const size_t base = (((size_t)b * h + 2 * i) * w + 2 * j) * c + ch;
-    const float s = b2f(x[base]) + b2f(x[base + c]) + b2f(x[base + (size_t)w * c]) + b2f(x[base + (size_t)w * c + c]);
-    y[k] = f2b(0.25f * s);
+    const int cg = c >> 3, ho = h >> 1, wo = w >> 1;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= wo * cg) return;
+    const int j = t / cg, g = t - j * cg;
+    for (int r = blockIdx.y; r < n * ho; r += gridDim.y) {
+        const int b = r / ho, i = r - b * ho;
+        const size_t base = (((size_t)b * h + 2 * i) * w + 2 * j) * c + 8 * g;
+        const size_t rs = (size_t)w * c;
+        const uint4 a = ld16(x + base), bq = ld16(x + base + c), cq = ld16(x + base + rs), d = ld16(x + base + rs + c);
+        const uint32_t* A = (const uint32_t*)&a; const uint32_t* B = (const uint32_t*)&bq;
+        const uint32_t* C = (const uint32_t*)&cq; const uint32_t* D = (const uint32_t*)&d;
+        uint4 o;
+        uint32_t* O = (uint32_t*)&o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float sl = lo_f(A[e]) + lo_f(B[e]) + lo_f(C[e]) + lo_f(D[e]);
+            const float sh = hi_f(A[e]) + hi_f(B[e]) + hi_f(C[e]) + hi_f(D[e]);
+            O[e] = pk(0.25f * sl, 0.25f * sh);
+        }
+        st16(y + ((size_t)r * wo + j) * c + 8 * g, o);
+    }
 }
 
+// adjoint of the pool: dx [n][h][w][c] = 0.25 dy [n][h/2][w/2][c]
 __global__ __launch_bounds__(256) void pool_bwd_kernel(const uint16_t* dy, uint16_t* dx, int n, int h, int w, int c) {
-    const long long total = (long long)n * h * w * c;
-    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= total) return;
-    const int ch = (int)(k % c);
-    long long q = k / c;
-    const int xx = (int)(q % w);
-    q /= w;
-    const int yy = (int)(q % h);
-    const int b = (int)(q / h);
-    dx[k] = f2b(0.25f * b2f(dy[(((size_t)b * (h / 2) + yy / 2) * (w / 2) + xx / 2) * c + ch]));
+    const int cg = c >> 3, ho = h >> 1, wo = w >> 1;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= w * cg) return;
+    const int xx = t / cg, g = t - xx * cg;
+    for (int r = blockIdx.y; r < n * h; r += gridDim.y) {
+        const int b = r / h, yy = r - b * h;
+        const uint4 v = ld16(dy + (((size_t)b * ho + (yy >> 1)) * wo + (xx >> 1)) * c + 8 * g);
+        const uint32_t* V = (const uint32_t*)&v;
+        uint4 o;
+        uint32_t* O = (uint32_t*)&o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) O[e] = pk(0.25f * lo_f(V[e]), 0.25f * hi_f(V[e]));
+        st16(dx + ((size_t)r * w + xx) * c + 8 * g, o);
+    }
 }
 
 // nearest-neighbour x2 upsampling; (h, w) are the input sizes.
 __global__ __launch_bounds__(256) void up_fwd_kernel(const uint16_t* x, uint16_t* y, int n, int h, int w, int c) {
-    const long long total = (long long)n * 4 * h * w * c;
-    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= total) return;
-    const int ch = (int)(k % c);
-    long long q = k / c;
-    const int xx = (int)(q % (2 * w));
-    q /= (2 * w);
-    const int yy = (int)(q % (2 * h));
-    const int b = (int)(q / (2 * h));
-    y[k] = x[(((size_t)b * h + yy / 2) * w + xx / 2) * c + ch];
+    const int cg = c >> 3, W2 = 2 * w, H2 = 2 * h;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= W2 * cg) return;
+    const int xx = t / cg, g = t - xx * cg;
+    for (int r = blockIdx.y; r < n * H2; r += gridDim.y) {
+        const int b = r / H2, yy = r - b * H2;
+        st16(y + ((size_t)r * W2 + xx) * c + 8 * g, ld16(x + (((size_t)b * h + (yy >> 1)) * w + (xx >> 1)) * c + 8 * g));
+    }
 }
 
+// adjoint of the upsampling: dx [n][h][w][c] = sum of the four dy it fed
 __global__ __launch_bounds__(256) void up_bwd_kernel(const uint16_t* dy, uint16_t* dx, int n, int h, int w, int c) {
-    const long long total = (long long)n * h * w * c;
+    const int cg = c >> 3;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= w * cg) return;
+    const int j = t / cg, g = t - j * cg;
+    for (int r = blockIdx.y; r < n * h; r += gridDim.y) {
+        const int b = r / h, i = r - b * h;
+        const size_t base = (((size_t)b * 2 * h + 2 * i) * 2 * w + 2 * j) * c + 8 * g;
+        const size_t rs = (size_t)2 * w * c;
+        const uint4 a = ld16(dy + base), bq = ld16(dy + base + c), cq = ld16(dy + base + rs), d = ld16(dy + base + rs + c);
+        const uint32_t* A = (const uint32_t*)&a; const uint32_t* B = (const uint32_t*)&bq;
+        const uint32_t* C = (const uint32_t*)&cq; const uint32_t* D = (const uint32_t*)&d;
+        uint4 o;
+        uint32_t* O = (uint32_t*)&o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            O[e] = pk(lo_f(A[e]) + lo_f(B[e]) + lo_f(C[e]) + lo_f(D[e]), hi_f(A[e]) + hi_f(B[e]) + hi_f(C[e]) + hi_f(D[e]));
+        st16(dx + ((size_t)r * w + j) * c + 8 * g, o);
+    }
+}
+
+// ReLU backward and the skip add, 8 elements (16 bytes) per thread: used
+// when the count is a multiple of 8 and every buffer is 16-byte aligned.
+// Per element the result is the scalar kernels' (out may alias an input).
+__global__ __launch_bounds__(256) void relu_bwd_vec_kernel(const uint16_t* dy, const uint16_t* y, uint16_t* dx,
+                                                           long long n8) {
     const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= total) return;
-    const int ch = (int)(k % c);
-    long long q = k / c;
-    const int j = (int)(q % w);
-    q /= w;
-    const int i = (int)(q % h);
-    const int b = (int)(q / h);
-    const size_t base = (((size_t)b * 2 * h + 2 * i) * 2 * w + 2 * j) * c + ch;
-    const size_t rs = (size_t)2 * w * c;
-    dx[k] = f2b(b2f(dy[base]) + b2f(dy[base + c]) + b2f(dy[base + rs]) + b2f(dy[base + rs + c]));
+    if (k >= n8) return;
+    const uint4 d = ((const uint4*)dy)[k], v = ((const uint4*)y)[k];
+    const uint32_t* D = (const uint32_t*)&d;
+    const uint32_t* V = (const uint32_t*)&v;
+    uint4 o;
+    uint32_t* O = (uint32_t*)&o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        O[e] = (lo_f(V[e]) > 0.f ? (D[e] & 0xffffu) : 0u) | (hi_f(V[e]) > 0.f ? (D[e] & 0xffff0000u) : 0u);
+    ((uint4*)dx)[k] = o;
+}
+
+__global__ __launch_bounds__(256) void add_vec_kernel(const uint16_t* a, const uint16_t* b, uint16_t* o, long long n8) {
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n8) return;
+    const uint4 x = ((const uint4*)a)[k], z = ((const uint4*)b)[k];
+    const uint32_t* X = (const uint32_t*)&x;
+    const uint32_t* Z = (const uint32_t*)&z;
+    uint4 r;
+    uint32_t* R = (uint32_t*)&r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) R[e] = pk(lo_f(X[e]) + lo_f(Z[e]), hi_f(X[e]) + hi_f(Z[e]));
+    ((uint4*)o)[k] = r;
 }
 
 // MSE over the nch real output channels: loss = sum (pred - tgt)^2 / (npix nch);
@@ -603,6 +664,7 @@ __global__ __launch_bounds__(256) void targets_kernel(const ChanDesc* desc, cons
 
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
+static inline bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // The LDS-staged kernel for rows of 64, 128 or 256 pixels, except with 32
 // input and 32 output channels: there a work-group has one K block, the
@@ -658,24 +720,34 @@ hipError_t launch_conv_wgrad(const WgradArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dx, long long n, hipStream_t st) {
-    relu_bwd_kernel<<<blocks_of(n), 256, 0, st>>>(dy, y, dx, n);
+    if (n % 8 == 0 && al16(dy) && al16(y) && al16(dx)) relu_bwd_vec_kernel<<<blocks_of(n / 8), 256, 0, st>>>(dy, y, dx, n / 8);
+    else relu_bwd_kernel<<<blocks_of(n), 256, 0, st>>>(dy, y, dx, n);
     return hipGetLastError();
 }
 
 hipError_t launch_add(const uint16_t* a, const uint16_t* b, uint16_t* o, long long n, hipStream_t st) {
-    add_kernel<<<blocks_of(n), 256, 0, st>>>(a, b, o, n);
+    if (n % 8 == 0 && al16(a) && al16(b) && al16(o)) add_vec_kernel<<<blocks_of(n / 8), 256, 0, st>>>(a, b, o, n / 8);
+    else add_kernel<<<blocks_of(n), 256, 0, st>>>(a, b, o, n);
     return hipGetLastError();
 }
 
+// grid of the row-wise pooling / upsampling kernels: x covers one output
+// row's (pixel, 8-channel group) pairs, y walks the output rows
+static dim3 row_grid(long long row_items, long long rows) {
+    return dim3((unsigned)((row_items + 255) / 256), (unsigned)std::min<long long>(rows, 65535));
+}
+
 hipError_t launch_pool(int dir, const uint16_t* in, uint16_t* out, int n, int h, int w, int c, hipStream_t st) {
-    if (dir == 0) pool_fwd_kernel<<<blocks_of((long long)n * (h / 2) * (w / 2) * c), 256, 0, st>>>(in, out, n, h, w, c);
-    else pool_bwd_kernel<<<blocks_of((long long)n * h * w * c), 256, 0, st>>>(in, out, n, h, w, c);
+    const int cg = c / 8;
+    if (dir == 0) pool_fwd_kernel<<<row_grid((long long)(w / 2) * cg, (long long)n * (h / 2)), 256, 0, st>>>(in, out, n, h, w, c);
+    else pool_bwd_kernel<<<row_grid((long long)w * cg, (long long)n * h), 256, 0, st>>>(in, out, n, h, w, c);
     return hipGetLastError();
 }
 
 hipError_t launch_up(int dir, const uint16_t* in, uint16_t* out, int n, int h, int w, int c, hipStream_t st) {
-    if (dir == 0) up_fwd_kernel<<<blocks_of((long long)n * 4 * h * w * c), 256, 0, st>>>(in, out, n, h, w, c);
-    else up_bwd_kernel<<<blocks_of((long long)n * h * w * c), 256, 0, st>>>(in, out, n, h, w, c);
+    const int cg = c / 8;
+    if (dir == 0) up_fwd_kernel<<<row_grid((long long)2 * w * cg, (long long)n * 2 * h), 256, 0, st>>>(in, out, n, h, w, c);
+    else up_bwd_kernel<<<row_grid((long long)w * cg, (long long)n * h), 256, 0, st>>>(in, out, n, h, w, c);
     return hipGetLastError();
 }
 

@@ -108,6 +108,27 @@ def test_conv_backward(env, ci, co):
     assert np.max(np.abs(host(dw) - 2 * rdw)) <= 4e-5 * np.max(np.abs(rdw))
 
 
+@pytest.mark.parametrize("n,h,w,c", [(3, 4, 256, 96), (1, 2, 128, 64)])
+def test_pool_and_up_wide_rows(env, n, h, w, c):
+    """Pooling and upsampling on rows wider than one block of 8-channel
+    groups (w c / 8 > 256), against the oracle."""
+    torch, nn = env
+    rng = np.random.default_rng(n * h * w * c)
+    x, xr = bf(torch, rng.normal(size=(n, h, w, c)))
+    p = torch.empty((n, h // 2, w // 2, c), dtype=torch.bfloat16, device="cuda")
+    nn.nn_pool2(0, x, p, n, h, w, c)
+    assert np.allclose(host(p), O.pool2(xr), rtol=2.0 ** -8, atol=1e-6)
+    gf = torch.empty((n, h, w, c), dtype=torch.bfloat16, device="cuda")
+    nn.nn_pool2(1, p, gf, n, h, w, c)
+    assert np.allclose(host(gf), O.pool2_backward(host(p)), rtol=2.0 ** -8, atol=1e-6)
+    u = torch.empty((n, 2 * h, 2 * w, c), dtype=torch.bfloat16, device="cuda")
+    nn.nn_up2(0, x, u, n, h, w, c)
+    assert np.array_equal(host(u), O.up2(xr))
+    gx = torch.empty((n, h, w, c), dtype=torch.bfloat16, device="cuda")
+    nn.nn_up2(1, u, gx, n, h, w, c)
+    assert np.allclose(host(gx), O.up2_backward(host(u)), rtol=2.0 ** -8, atol=1e-6)
+
+
 def test_small_kernels(env):
     torch, nn = env
     rng = np.random.default_rng(11)
@@ -134,6 +155,14 @@ def test_small_kernels(env):
     r = torch.empty_like(x)
     nn.nn_relu_bwd(x, y, r)
     assert np.array_equal(host(r), xr * (yr > 0))
+    # unaligned views with an odd count take the one-element-per-thread kernels
+    xs, ys = x.view(-1)[1:38], y.view(-1)[3:40]
+    s2 = torch.zeros(64, dtype=torch.bfloat16, device="cuda")[1:38]
+    nn.nn_add(xs, ys, s2)
+    assert np.allclose(host(s2), xr.reshape(-1)[1:38] + yr.reshape(-1)[3:40], rtol=2.0 ** -8, atol=1e-6)
+    r2 = torch.zeros(64, dtype=torch.bfloat16, device="cuda")[1:38]
+    nn.nn_relu_bwd(xs, ys, r2)
+    assert np.array_equal(host(r2), xr.reshape(-1)[1:38] * (yr.reshape(-1)[3:40] > 0))
 
 
 def test_mse_and_adam(env):
