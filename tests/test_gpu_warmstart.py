@@ -10,7 +10,7 @@ float64.  Checked: the network's raw errors are far below those of the
 state at rest; every channel converges from both starts and ends in the
 same steady state; it needs at least 10% fewer steps in total over the
 channels both converge on (measured here: 21%; on 256 held-out channels:
-median 88 301 against 120 751 steps, per-channel median ratio 1.34).  The
+median 88 301 against 120 751 steps, per-channel median ratio 1.33).  The
 remaining steps are set
 by the slow viscous, thermal and interface modes, which a prediction a few
 percent off shortens only logarithmically.
