@@ -89,3 +89,29 @@ def test_create_rejects_bad_arguments():
 def test_strerror():
     for s in (0, -1, -2, -3, -4, -5, -99):
         assert isinstance(lbm.lbm_strerror(s), str)
+
+
+def test_network_calls_reject_bad_shapes():
+    """Shape and pointer checks of the network entry points return before
+    any launch (dummy non-null addresses are never dereferenced)."""
+    from paper_2210_07501_amd import nn
+    L = nn.load()
+    p = ctypes.c_void_p(256)
+    E = lbm.LBM_EINVAL
+    # pooling / upsampling: c a multiple of 8, even sizes for pooling, non-null buffers
+    assert L.nn_pool2(0, p, p, 1, 4, 64, 12, None) == E
+    assert L.nn_pool2(0, p, p, 1, 5, 64, 32, None) == E
+    assert L.nn_pool2(0, None, p, 1, 4, 64, 32, None) == E
+    assert L.nn_up2(0, p, p, 1, 4, 64, 4, None) == E
+    assert L.nn_up2(1, p, None, 1, 4, 64, 32, None) == E
+    # convolution: widths multiple of 64, channels multiple of 32 up to 96
+    assert L.nn_conv3x3_fwd(p, p, None, p, None, 0, 1, 4, 96, 32, 32, 0, None) == E
+    assert L.nn_conv3x3_fwd(p, p, None, p, None, 0, 1, 4, 64, 48, 32, 0, None) == E
+    assert L.nn_conv3x3_fwd(p, p, None, p, None, 0, 1, 4, 64, 32, 128, 0, None) == E
+    assert L.nn_conv3x3_bwd_data(p, p, p, 1, 4, 64, 32, 16, None) == E
+    # weight gradient: a workspace smaller than the one asked for
+    need = nn.nn_conv3x3_wgrad_workspace(1, 4, 64, 32, 32)
+    assert L.nn_conv3x3_bwd_weight(p, p, p, None, p, need - 4, 0, 1, 4, 64, 32, 32, None) == E
+    # elementwise: negative counts
+    assert L.nn_add(p, p, p, -1, None) == E
+    assert L.nn_relu_bwd(p, p, p, -1, None) == E
