@@ -10,7 +10,10 @@ Which mistake each pin catches (one line each):
   stationary tanh           sign of the sharpening coefficient theta
   Laplace pressure          capillary term -sigma kappa n, delta_s = 1.5 W |grad phi|^2
   NF / SRF vs Sec. 2        Marangoni term, dsigma/dT, roll count and flow direction
+  residual properties       norms, the T_ref offset and the 1/K of the steady-state residual
+  residual decay rate       energy-LBM diffusivity; the residual tracks the slowest mode
 """
+import math
 import numpy as np
 import pytest
 
@@ -170,3 +173,47 @@ def test_thermocapillary_channel_vs_section_2(kind):
     assert 0.5 < np.max(np.abs(ui)) / np.max(np.abs(sharp)) < 0.8
     # shape: correlation of the profile with the prediction
     assert np.dot(ui, pred) / np.linalg.norm(ui) / np.linalg.norm(pred) > 0.999
+
+
+def test_residual_definition_properties():
+    # The steady-state residual is a reading (the paper defines none): every
+    # K steps, the larger of the relative changes of u and of T - T_ref,
+    # divided by K.  Exact properties of that definition: scaling u (or
+    # T - T_ref) by (1 - eps) between two checks gives eps / K.
+    rng = np.random.default_rng(5)
+    K, T_ref, e1, e2 = 100, 1.3, 1e-3, 3e-3
+    ux, uy = rng.normal(size=(8, 16)), rng.normal(size=(8, 16))
+    T = T_ref + rng.normal(size=(8, 16))
+    cur = {"ux": ux, "uy": uy, "T": T}
+    assert orc.residual(cur, cur, K, T_ref) == 0.0
+    prev_u = {"ux": ux * (1 - e1), "uy": uy * (1 - e1), "T": T}
+    assert orc.residual(prev_u, cur, K, T_ref) == pytest.approx(e1 / K, rel=1e-12)
+    prev_T = {"ux": ux, "uy": uy, "T": T_ref + (T - T_ref) * (1 - e2)}
+    assert orc.residual(prev_T, cur, K, T_ref) == pytest.approx(e2 / K, rel=1e-12)
+    both = {"ux": ux * (1 - e1), "uy": uy * (1 - e1), "T": T_ref + (T - T_ref) * (1 - e2)}
+    assert orc.residual(both, cur, K, T_ref) == pytest.approx(max(e1, e2) / K, rel=1e-12)
+    # no flow at all: the velocity part is zero, the temperature part decides
+    still = {"ux": 0 * ux, "uy": 0 * uy, "T": T}
+    prev_still = {"ux": 0 * ux, "uy": 0 * uy, "T": T_ref + (T - T_ref) * (1 - e2)}
+    assert orc.residual(prev_still, still, K, T_ref) == pytest.approx(e2 / K, rel=1e-12)
+
+
+def test_residual_decays_at_the_slowest_conduction_mode():
+    # Conduction only (sigma constant, equal conductivities): the cold
+    # start's linear T differs from the steady state by modes
+    # sin(n pi (y + 1/2) / H) cos(2 pi x / l) of the heat equation between
+    # isothermal walls (Sec. 5); the slowest decays at
+    # alpha ((2 pi / l)^2 + (pi / H)^2), H = ny, and late in the run the
+    # residual falls by exp(-lambda K) per check.
+    c = inputs.cfg(nx=32, ny=16, b=8.0, sigma_T=0.0, sigma_TT=0.0, k_a=0.1, k_b=0.1, mu_a=0.1, mu_b=0.1)
+    K = 100
+    o = orc.Oracle(c)
+    o.init_cold()
+    prev, rs = o.fields(), []
+    for _ in range(12):
+        o.step(K)
+        cur = o.fields()
+        rs.append(orc.residual(prev, cur, K, c["T_ref"]))
+        prev = cur
+    lam = 0.1 * ((2 * math.pi / 32) ** 2 + (math.pi / 16) ** 2)
+    assert rs[-1] / rs[-2] == pytest.approx(math.exp(-lam * K), rel=2e-3)
