@@ -44,3 +44,20 @@ def run_oracle(cfg, steps, fields=None):
         o.init_fields(*fields)
     o.step(steps)
     return o
+
+
+def oracle_sensitivity(cfg, steps, fields=None, seed=1):
+    """Conditioning of a case: relative max-norm change of the oracle's
+    populations (f, g, h) and phi after `steps` when its initial populations
+    are perturbed by one ulp (relative 2^-52, seeded signs).  Two float64
+    implementations that round differently cannot agree more closely than
+    this, whatever the bar."""
+    a = run_oracle(cfg, 0, fields)
+    b = run_oracle(cfg, 0, fields)
+    rng = np.random.default_rng(seed)
+    b.set_state(b.pop * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=b.pop.shape)))
+    a.step(steps)
+    b.step(steps)
+    out = {name: rel_maxnorm(b.pop[d], a.pop[d]) for d, name in enumerate("fgh")}
+    out["phi"] = rel_maxnorm(b.fields()["phi"], a.fields()["phi"])
+    return out
