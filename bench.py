@@ -71,6 +71,33 @@ def run_gpu(cfg, prec, steps, warmup, tile):
     return dict(nodes=nodes, ms_total=ms, wall_s=wall, kernel_ms=kms, res=res)
 
 
+def copy_ceiling(nbytes=1 << 30, reps=20):
+    """Read + write bandwidth of a plain 1 GiB device copy (GB/s), timed with
+    HIP events on the current stream: the faster of the runtime's copy and
+    an elementwise float32 copy kernel.  The practical HBM ceiling the step
+    is also compared with."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    for fn in (lambda: dst.copy_(src), lambda: torch.mul(src, 1.0, out=dst)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        best = max(best, 2.0 * nbytes / (ms * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
 def cpu_baseline(target_s=12.0, target_1=6.0):
     """The FP64 oracle, as it stands, on the 256 x 128 sub-run of the same
     channel geometry (scaled by 1/16), timed on this host's cores: all
@@ -195,6 +222,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("bench: calibration copy of 1 GiB x 3 done")
+    copy_gbs = copy_ceiling()
+    log("bench: device copy ceiling %.0f GB/s (read + write)" % copy_gbs)
     precs = {"both": (lbm.LBM_FP64, lbm.LBM_FP32_DEV), "fp64": (lbm.LBM_FP64,),
              "fp32": (lbm.LBM_FP32_DEV,)}[args.precision]
     out = {}
@@ -219,7 +248,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(traffic * r["nodes"]) if traffic else None,
                 "kernel_ms": round(launch_ms, 4), "kernel_ms_back_to_back": round(r["kernel_ms"], 4),
-                "bytes_per_update": bpu}
+                "bytes_per_update": bpu, "copy_gbs": round(copy_gbs, 1),
+                "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     if lbm.LBM_FP64 not in out or lbm.LBM_FP32_DEV not in out:
         # partial runs (profiling, tile sweeps) print the per-precision numbers only
