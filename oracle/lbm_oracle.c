@@ -40,11 +40,10 @@
  *
  * Parity unpinned: no pin separates the following, so they are checked only
  * by reading them against Sec. 4.2 (and by GPU parity, which implements them
- * too).  They are the pressure correction p = p* + F_p . u / 2, the sign of
- * F_p, and the (1 - omega / 2) factor of the second-order forcing term of the
- * g collision; all are O(u . grad p), which is zero at rest and below the
- * pins' resolution in creeping flow.  Also unpinned are the T ghost rows of
- * the sigma(T) stencil, which act only where an interface meets a wall.
+ * too).  The first is the (1 - omega / 2) factor of the second-order forcing
+ * term of the g collision's shear mode; it changes a relaxing interface's
+ * rate by 0.1%.  The second is the T ghost rows of the sigma(T) stencil,
+ * which act only where an interface meets a wall.
  */
 #include <math.h>
 #include <stdlib.h>
