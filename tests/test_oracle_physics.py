@@ -146,11 +146,15 @@ def test_laplace_pressure_of_static_drop():
     assert 0.85 < dp / (s0 / R) < 1.0
 
 
-@pytest.mark.parametrize("kind", ["nf", "srf"])
+@pytest.mark.parametrize("kind", ["nf", "srf", "nf_mu"])
 def test_thermocapillary_channel_vs_section_2(kind):
     # 64 x 32 channel, a = b = 16: NF (sigma_TT = 0) and SRF (sigma_T = 0).
-    c = inputs.cfg(nx=64, ny=32, b=16.0, sigma_T=(-2e-4 if kind == "nf" else 0.0),
-                   sigma_TT=(2e-4 if kind == "srf" else 0.0))
+    # nf_mu: unequal layers (b = 10, a = 22) of viscosity ratio mu_a / mu_b
+    # = 0.25; with a != b the interface velocity depends on which layer is
+    # the more viscous (swapping them moves the ratio below to 1.27).
+    extra = dict(b=10.0, mu_a=0.025) if kind == "nf_mu" else dict(b=16.0)
+    c = inputs.cfg(nx=64, ny=32, sigma_T=(0.0 if kind == "srf" else -2e-4),
+                   sigma_TT=(2e-4 if kind == "srf" else 0.0), **extra)
     o = orc.Oracle(c)
     o.init_cold()
     o.step(20000)
@@ -160,8 +164,8 @@ def test_thermocapillary_channel_vs_section_2(kind):
     ui = an.interface_profile(F["ux"], F["phi"])
     # roll count and direction (Sec. 6): NF 4 rolls away from the hot spot
     # at x = 0, SRF 8 rolls toward it
-    assert an.count_rolls(F["uy"], c) == (4 if kind == "nf" else 8)
-    if kind == "nf":
+    assert an.count_rolls(F["uy"], c) == (8 if kind == "srf" else 4)
+    if kind != "srf":
         assert ui[8] > 0 and ui[56] < 0
     else:
         assert ui[8] < 0 and ui[56] > 0
