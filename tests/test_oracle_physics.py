@@ -14,6 +14,7 @@ Which mistake each pin catches (one line each):
   residual decay rate       energy-LBM diffusivity; the residual tracks the slowest mode
   Stokes relaxation vs rho  the pressure force -grad(p* - rho c_s^2) and the pressure
                             correction p* + F_p . u / 2 at a density jump
+  two-layer start-up        inertia with a density jump: rho(phi) and which layer is dense
 """
 import math
 import numpy as np
@@ -257,3 +258,39 @@ def test_interface_relaxation_is_density_independent_in_the_stokes_limit():
     r1 = _relaxation_rate(1.0)
     r2 = _relaxation_rate(2.0)
     assert r1 > 0 and r2 == pytest.approx(r1, rel=3e-2)
+
+
+def test_two_layer_startup_decays_at_the_closed_form_rate():
+    # Flow started from rest by a uniform body force between the walls, in
+    # two layers of equal viscosity and unequal density and thickness.  The
+    # momentum equation rho du/dt = mu d2u/dy2 + F (what the Sec. 4.2 LBM
+    # recovers for this x-invariant flow) approaches its steady state at the
+    # smallest eigenvalue lambda of the two-layer problem: with
+    # k^2 = lambda rho / mu in each layer, u = A sin(k_b (y + b)) below and
+    # B sin(k_a (a - y)) above, continuous in u and mu du/dy at the
+    # interface.  Measured 0.993 of the closed form; swapping which layer is
+    # dense gives 0.65.
+    from scipy.optimize import brentq
+    ny, b, mu, ra, rb = 32, 10.0, 0.1, 1.0, 2.0
+    a = ny - b
+
+    def disp(lam):
+        ka, kb = math.sqrt(lam * ra / mu), math.sqrt(lam * rb / mu)
+        return kb * math.cos(kb * b) * math.sin(ka * a) + ka * math.cos(ka * a) * math.sin(kb * b)
+
+    grid = np.linspace(1e-6, 5e-3, 20000)
+    vals = np.array([disp(v) for v in grid])
+    i = int(np.nonzero(vals[:-1] * vals[1:] < 0)[0][0])
+    lam0 = brentq(disp, grid[i], grid[i + 1])
+    c = inputs.cfg(nx=4, ny=ny, b=b, rho_a=ra, rho_b=rb, mu_a=mu, mu_b=mu, sigma_T=0.0, sigma_TT=0.0, dT=0.0,
+                   Fx_ext=1e-6)
+    o = orc.Oracle(c)
+    o.init_cold()
+    us = []
+    for _ in range(8):
+        o.step(500)
+        us.append(o.fields()["ux"][:, 0].copy())
+    d1 = np.max(np.abs(us[5] - us[4]))
+    d2 = np.max(np.abs(us[7] - us[6]))
+    lam = -math.log(d2 / d1) / 1000.0
+    assert lam == pytest.approx(lam0, rel=3e-2)
