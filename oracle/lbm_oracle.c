@@ -41,9 +41,11 @@
  * Parity unpinned: no pin separates the following, so they are checked only
  * by reading them against Sec. 4.2 (and by GPU parity, which implements them
  * too).  The first is the (1 - omega / 2) factor of the second-order forcing
- * term of the g collision's shear mode; it changes a relaxing interface's
- * rate by 0.1%.  The second is the T ghost rows of the sigma(T) stencil,
- * which act only where an interface meets a wall.
+ * term of the g collision's shear mode; its effect grows with the Mach
+ * number (0.1% of a slow interface relaxation, 40% of a fast one) and
+ * vanishes in the incompressible limit every closed form here assumes.  The
+ * second is the T ghost rows of the sigma(T) stencil, which act only where
+ * an interface meets a wall.
  */
 #include <math.h>
 #include <stdlib.h>
