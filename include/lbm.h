@@ -26,8 +26,9 @@
  *
  * Every call returns an int status (LBM_OK = 0, negative on error) except
  * lbm_destroy and lbm_strerror.  A context is used by one host thread at a
- * time.  All work is ordered on the context's HIP stream; only lbm_fields,
- * lbm_residual, lbm_get_state, lbm_solve and lbm_profile_steps synchronise.
+ * time.  All work, set-up copies included, is ordered on the context's HIP
+ * stream.  lbm_step only enqueues; every other call that touches the device
+ * synchronises that stream (never the whole device) before it returns.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -143,7 +144,8 @@ int lbm_set_state(lbm_ctx* ctx, int32_t inst, const double* pop);
 
 /* Time n back-to-back launches of the fused step kernel alone with HIP
  * events on the context stream; *ms receives the average per launch.
- * Advances the state by n steps.  Synchronises. */
+ * Advances the state by n steps without the residual checks (the next check
+ * reports its own step index).  Synchronises. */
 int lbm_profile_steps(lbm_ctx* ctx, int64_t n, double* ms);
 
 /* Tile shape of the fused step kernel: tx x ty nodes per workgroup from the
