@@ -38,14 +38,13 @@
  *   - anti-bounce-back wall temperature taken at the boundary node's column;
  *   - phi at the walls: specular (free-slip) reflection.
  *
- * Parity unpinned: no pin separates the following, so they are checked only
- * by reading them against Sec. 4.2 (and by GPU parity, which implements them
- * too).  The first is the (1 - omega / 2) factor of the second-order forcing
- * term of the g collision's shear mode; its effect grows with the Mach
- * number (0.1% of a slow interface relaxation, 40% of a fast one) and
- * vanishes in the incompressible limit every closed form here assumes.  The
- * second is the T ghost rows of the sigma(T) stencil, which act only where
- * an interface meets a wall.
+ * Pins (tests/test_oracle_maps.py, test_oracle_physics.py, test_analytic.py)
+ * cover every term: the forced central-moment relaxation of each collision
+ * is checked moment by moment against Secs. 4.1-4.3 (the (1 - omega / 2)
+ * factor of the shear modes included), and the T ghost rows by a vertical
+ * interface meeting both walls in a linear temperature field, where the
+ * wall rows must carry the same Marangoni force per sigma'(T) as the rows
+ * between them.
  */
 #include <math.h>
 #include <stdlib.h>

@@ -35,6 +35,7 @@ MUT = {
  "curvature_sign": [("double curv = dnx_dx + dny_dy;", "double curv = -(dnx_dx + dny_dy);")],
  "pressure_force_sign": [("s.Fpx = -dvx;", "s.Fpx = dvx;"), ("s.Fpy = -dvy;", "s.Fpy = dvy;")],
  "g_forcing_factor": [("(1.0 - 0.5 * w_nu) * s2d", "s2d")],
+ "g_forcing_factor_11": [("+ (1.0 - 0.5 * w) * s[r];", "+ (r == 5 ? 1.0 : 1.0 - 0.5 * w) * s[r];")],
  "f_wall_bounce_back": [("POP(post, 0, mirror_y(a), j, is)", "POP(post, 0, opposite(a), j, i)")],
  "T_ghost_mirror": [("= 2.0 * T_bottom(P, i) - P1(w->T, 0, i);", "= P1(w->T, 0, i);"),
                     ("= 2.0 * P->T_c - P1(w->T, ny - 1, i);", "= P1(w->T, ny - 1, i);")],

@@ -257,3 +257,143 @@ def test_regime_boundaries_of_the_closed_form():
         return abs(an.U_tt(ch)) / abs(an.U_t(ch)), an.count_rolls(an.velocity(ch, X, Y)[1], c)
     assert at(3.5)[0] < 1.0 < at(3.6)[0]
     assert at(2.0)[1] == 4 and at(5.0)[1] == 4 and at(5.2)[1] == 8
+
+
+def _fd_stokes_interface_velocity(cfg, weights, x, M=8):
+    """Richardson extrapolation of _fd_stokes_once over grids 1/(2M) and
+    1/(4M): a sheet on the evaluation plane makes u(0) first-order accurate."""
+    return 2 * _fd_stokes_once(cfg, weights, x, 2 * M) - _fd_stokes_once(cfg, weights, x, M)
+
+
+def _fd_stokes_once(cfg, weights, x, M):
+    """Independent numerical check of the layered closed form: u_x at the
+    cold-start interface plane y = 0 of Stokes flow in one fluid layer of
+    viscosity mu_b between no-slip walls at y = -b and y = a, driven by
+    Marangoni stress sheets at the lattice rows y_k = j - (b - 1/2), sheet k
+    carrying the fraction weights[j] of the stress d(sigma)/dx at its own
+    height.  Equal viscosities and conductivities only (then the temperature
+    is the conduction field of the walls, whatever the interface does).
+    Every Fourier mode is solved by finite differences on a grid of spacing
+    1/(2M): the conduction profile (T'' = k^2 T with the wall values) and the
+    stream function, mu (D^2 - k^2)^2 psi = -dF/dy with psi = psi' = 0 at the
+    walls, the sheets as discrete delta functions; u = psi'."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    nx, ny, b = int(cfg["nx"]), int(cfg["ny"]), float(cfg["b"])
+    a = ny - b
+    K = 2 * np.pi / (nx / int(cfg["n_waves"]))
+    mu = float(cfg["mu_b"])
+    hgrid = 1.0 / (2 * M)
+    N = int(round((a + b) / hgrid))
+    ygrid = -b + hgrid * np.arange(N + 1)
+
+    def conduction(k, lo, hi):
+        # T'' - k^2 T = 0 on the grid with T(-b) = lo, T(a) = hi
+        n = N - 1
+        main = np.full(n, -2.0 / hgrid ** 2 - k * k)
+        off = np.full(n - 1, 1.0 / hgrid ** 2)
+        A = sp.diags([off, main, off], [-1, 0, 1], format="csc")
+        rhs = np.zeros(n)
+        rhs[0] -= lo / hgrid ** 2
+        rhs[-1] -= hi / hgrid ** 2
+        return np.concatenate([[lo], spla.spsolve(A, rhs), [hi]])
+
+    Tbar = conduction(0.0, cfg["T_h"], cfg["T_c"])           # mean part
+    A1 = conduction(K, cfg["dT"], 0.0)                         # cos(Kx) amplitude
+    s1, s2, Tr = cfg["sigma_T"], cfg["sigma_TT"], cfg["T_ref"]
+    # d sigma / dx = sigma'(T) dT/dx with T = Tbar + A1 cos Kx:
+    #   = -K A1 (s1 + 2 s2 (Tbar - T_ref)) sin Kx - s2 K A1^2 sin 2Kx
+    amp = {1: -K * A1 * (s1 + 2 * s2 * (Tbar - Tr)), 2: -s2 * K * A1 ** 2}
+    j = np.arange(ny)
+    yk = j - (b - 0.5)
+    idx = np.rint((yk + b) / hgrid).astype(int)
+    assert np.allclose(ygrid[idx], yk)
+    i0 = int(round(b / hgrid))                                 # y = 0
+    n = N - 1                                                  # unknowns psi_1 .. psi_{N-1}
+    u = np.zeros_like(x, dtype=float)
+    for m, am in amp.items():
+        k = m * K
+        if np.max(np.abs(am)) == 0.0:
+            continue
+        # coupled second-order form (better conditioned than the biharmonic):
+        # w = (D^2 - k^2) psi on nodes 1..N-1, (D^2 - k^2) w = -F'/mu there,
+        # psi_0 = psi_N = 0 and psi' = 0 at the walls through the ghost
+        # psi_-1 = psi_1, which gives w_0 = 2 psi_1 / h^2 (and likewise on top).
+        F = np.zeros(N + 1)
+        F[idx] = weights * am[idx] / hgrid       # sheets as discrete deltas
+        dF = np.zeros(N + 1)
+        dF[1:-1] = (F[2:] - F[:-2]) / (2 * hgrid)
+        h2 = hgrid * hgrid
+        nps = N - 1                              # psi_1 .. psi_{N-1}
+        nw = N + 1                               # w_0 .. w_N
+        A = sp.lil_matrix((nps + nw, nps + nw))
+        rhs = np.zeros(nps + nw)
+        for r in range(nps):                     # node i = r + 1
+            i = r + 1
+            if i - 1 >= 1:
+                A[r, r - 1] = 1 / h2
+            A[r, r] = -2 / h2 - k * k
+            if i + 1 <= N - 1:
+                A[r, r + 1] = 1 / h2
+            A[r, nps + i] = -1.0
+        for i in range(1, N):                    # vorticity equations
+            r = nps + i
+            A[r, nps + i - 1] = 1 / h2
+            A[r, nps + i] = -2 / h2 - k * k
+            A[r, nps + i + 1] = 1 / h2
+            rhs[r] = -dF[i] / mu
+        A[nps + 0, nps + 0] = 1.0
+        A[nps + 0, 0] = -2 / h2
+        A[nps + N, nps + N] = 1.0
+        A[nps + N, nps - 1] = -2 / h2
+        sol = spla.spsolve(A.tocsc(), rhs)
+        psi = np.zeros(N + 1)
+        psi[1:-1] = sol[:nps]
+        du0 = (psi[i0 + 1] - psi[i0 - 1]) / (2 * hgrid)
+        u += du0 * np.sin(k * x)
+    return u
+
+
+@pytest.mark.parametrize("kind", ["nf", "srf"])
+def test_sharp_closed_form_against_finite_difference_stokes(kind):
+    # The Sec. 2 interface velocity (closed form) equals the numerical Stokes
+    # solution driven by one stress sheet on the interface plane.
+    cfg = inputs.cfg(nx=256, ny=128, b=64.0, sigma_T=-2e-4 if kind == "nf" else 0.0,
+                     sigma_TT=0.0 if kind == "nf" else 2e-4)
+    x = np.arange(0, 256, 8, dtype=float)
+    # a sheet exactly on y = 0: shift the lattice rows by half a cell
+    c2 = dict(cfg, b=cfg["b"] + 0.5)
+    w = np.zeros(cfg["ny"])
+    w[int(cfg["b"])] = 1.0                       # row j = b sits on y = 0 of c2
+    fd = _fd_stokes_interface_velocity(c2, w, x)
+    exact = an.interface_velocity(an.channel_from_config(c2), x)
+    assert np.max(np.abs(fd - exact)) <= 2e-4 * np.max(np.abs(exact))
+
+
+@pytest.mark.parametrize("kind", ["nf", "srf"])
+def test_diffuse_interface_velocity_against_finite_difference_stokes(kind):
+    # The diffuse-interface prediction (stress spread over the rows of the
+    # sampled tanh with weights 1.5 W |d phi/dy|^2, each row's share taken as
+    # the sharp solution of a channel whose interface sits on that row) equals
+    # the numerical Stokes solution driven by the same spread stress as body-
+    # force sheets in one fluid, and it falls below the sharp value by about
+    # the discrete integral of the weights (0.939 at W = 4) times the smearing
+    # loss.  The two models differ in what holds v = 0: the predictor puts an
+    # impermeable plane under each sheet, the numerical solution none.  For
+    # sheets within two cells of the plane that changes u(0) by < 1e-4, and
+    # over the weights of a W = 4 interface by 2.3e-4 (NF) and 1.0e-4 (SRF) of
+    # the peak -- far below the 2% bar the predictor serves.
+    cfg = inputs.analytic_channel(kind)
+    x = np.arange(0, cfg["nx"], 16, dtype=float)
+    W, b, ny = cfg["W"], cfg["b"], cfg["ny"]
+    yk = np.arange(-2, ny + 2) - (b - 0.5)
+    phi = 0.5 * (1 + np.tanh(-2 * yk / W))
+    g = np.zeros_like(phi)
+    g[1:-1] = (phi[2:] - phi[:-2]) / 2
+    weights = (1.5 * W * g ** 2)[2:-2]
+    fd = _fd_stokes_interface_velocity(cfg, weights, x, M=4)
+    pred = an.diffuse_interface_velocity(cfg, x)
+    assert np.max(np.abs(fd - pred)) <= 3e-4 * np.max(np.abs(pred))
+    sharp = an.interface_velocity(an.channel_from_config(cfg), x)
+    ratio = np.max(np.abs(pred)) / np.max(np.abs(sharp))
+    assert 0.85 < ratio < weights.sum() < 0.95

@@ -169,3 +169,97 @@ def test_hydro_collision_shear_relaxation():
     assert central(out, 1, 1) == pytest.approx(o_in + om * (vphi * ux * uy - o_in), rel=1e-9)
     assert central(out, 2, 0) + central(out, 0, 2) == pytest.approx(
         2 * p * cs2 + vphi * (ux * ux + uy * uy), rel=1e-12)
+
+
+def _central(v, ex, ey, ux, uy, m, n):
+    # central moment by its definition, sum_a v_a (e_ax - u_x)^m (e_ay - u_y)^n
+    return float(np.sum(v * (ex - ux) ** m * (ey - uy) ** n))
+
+
+@pytest.mark.parametrize("rho,om", [(1.0, 1.37), (1.8, 0.62)])
+def test_hydro_collision_all_central_moments_with_forces(rho, om):
+    # Sec. 4.2, Eq. (centralmomentrelaxationtwofluidmotion) with the source
+    # moments sigma_mn printed there, at a node carrying a surface-tension force
+    # F_t and a pressure force F_p: every post-collision central moment of the
+    # oracle's output (computed here by brute force from its definition) equals
+    #   eta_mn + omega_mn (eta_mn^eq - eta_mn) + (1 - omega_mn / 2) sigma_mn,
+    # with omega_2d = omega_11 = omega_nu and every other rate 1, the diagonal
+    # pair evolved as trace 2s and deviator 2d.  This separates the (1 - omega/2)
+    # factor of the shear modes (dropping it moves eta_2d by omega sigma_2d / 2).
+    _, _, w, ex, ey = orc.tables()
+    rng = np.random.default_rng(17)
+    g = w / 3 + rng.uniform(-2e-3, 2e-3, 9)
+    cs2 = 1 / 3
+    Ftx, Fty, Fpx, Fpy = 3e-3, -2e-3, 4e-3, 2.5e-3
+    ux = (np.sum(g * ex) + 0.5 * cs2 * Ftx) / (rho * cs2)
+    uy = (np.sum(g * ey) + 0.5 * cs2 * Fty) / (rho * cs2)
+    Gam = Fpx * ux + Fpy * uy
+    p = g.sum() + 0.5 * Gam
+    vphi = p - rho * cs2
+    out = orc.collide_g_node(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om)
+    c_in = {(m, n): _central(g, ex, ey, ux, uy, m, n) for m in range(3) for n in range(3)}
+    c_out = {(m, n): _central(out, ex, ey, ux, uy, m, n) for m in range(3) for n in range(3)}
+    eq = {(0, 0): p, (1, 0): -vphi * ux, (0, 1): -vphi * uy,
+          (2, 0): p * cs2 + vphi * ux * ux, (0, 2): p * cs2 + vphi * uy * uy, (1, 1): vphi * ux * uy,
+          (2, 1): -vphi * (ux * ux + cs2) * uy, (1, 2): -vphi * (uy * uy + cs2) * ux,
+          (2, 2): cs2 ** 3 * rho + vphi * (ux * ux + cs2) * (uy * uy + cs2)}
+    src = {(0, 0): Gam, (1, 0): cs2 * Ftx - ux * Gam, (0, 1): cs2 * Fty - uy * Gam,
+           (2, 0): 2 * cs2 * Fpx * ux + (ux * ux + cs2) * Gam, (0, 2): 2 * cs2 * Fpy * uy + (uy * uy + cs2) * Gam,
+           (1, 1): cs2 * (Fpx * uy + Fpy * ux) + ux * uy * Gam, (2, 1): 0.0, (1, 2): 0.0, (2, 2): 0.0}
+
+    def relax(x, x_eq, s, rate):
+        return x + rate * (x_eq - x) + (1 - rate / 2) * s
+
+    want = {k: relax(c_in[k], eq[k], src[k], 1.0) for k in [(0, 0), (1, 0), (0, 1), (2, 1), (1, 2), (2, 2)]}
+    want[(1, 1)] = relax(c_in[(1, 1)], eq[(1, 1)], src[(1, 1)], om)
+    two_s = relax(c_in[(2, 0)] + c_in[(0, 2)], eq[(2, 0)] + eq[(0, 2)], src[(2, 0)] + src[(0, 2)], 1.0)
+    two_d = relax(c_in[(2, 0)] - c_in[(0, 2)], eq[(2, 0)] - eq[(0, 2)], src[(2, 0)] - src[(0, 2)], om)
+    want[(2, 0)] = 0.5 * (two_s + two_d)
+    want[(0, 2)] = 0.5 * (two_s - two_d)
+    scale = max(abs(v) for v in c_out.values())
+    for k in want:
+        assert abs(c_out[k] - want[k]) <= 1e-13 * scale, (k, c_out[k], want[k])
+    # the shear-mode sources are large enough here to show the factor: dropping
+    # it would move eta_2d and eta_11 by far more than the tolerance
+    assert abs(om / 2 * (src[(2, 0)] - src[(0, 2)])) > 1e4 * 1e-13 * scale
+    assert abs(om / 2 * src[(1, 1)]) > 1e4 * 1e-13 * scale
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0), (0.04, -0.03)])
+def test_ace_collision_all_central_moments(u):
+    # Sec. 4.1: post-collision central moments of the conservative Allen-Cahn
+    # collision -- the first relax at omega_phi to M theta n, every other one
+    # equals its equilibrium (phi, -, -, phi c_s^2, phi c_s^2, 0, 0, 0, phi c_s^4)
+    # -- checked by brute force on the oracle's output at a moving node.
+    _, _, w, ex, ey = orc.tables()
+    ux, uy = u
+    rng = np.random.default_rng(18)
+    f = w * 0.6 + rng.uniform(-1e-3, 1e-3, 9)
+    phi = f.sum()
+    cs2 = 1 / 3
+    M, theta, om, nx, ny = 0.02, 0.25, 1.2, 0.6, -0.8
+    out = orc.collide_f_node(f, phi, ux, uy, nx, ny, theta, M, om)
+    k10, k01 = _central(f, ex, ey, ux, uy, 1, 0), _central(f, ex, ey, ux, uy, 0, 1)
+    want = {(0, 0): phi, (1, 0): k10 + om * (M * theta * nx - k10), (0, 1): k01 + om * (M * theta * ny - k01),
+            (2, 0): phi * cs2, (0, 2): phi * cs2, (1, 1): 0.0, (2, 1): 0.0, (1, 2): 0.0, (2, 2): phi * cs2 * cs2}
+    for k, v in want.items():
+        assert abs(_central(out, ex, ey, ux, uy, *k) - v) < 1e-15, k
+
+
+@pytest.mark.parametrize("u", [(0.0, 0.0), (0.05, 0.02)])
+def test_energy_collision_all_central_moments(u):
+    # Sec. 4.3: the first central moments of h relax at omega_T to zero, the
+    # others take the equilibrium (T, 0, 0, T c_s^2, T c_s^2, 0, 0, 0, T c_s^4).
+    _, _, w, ex, ey = orc.tables()
+    ux, uy = u
+    rng = np.random.default_rng(19)
+    h = w * 1.1 + rng.uniform(-2e-3, 2e-3, 9)
+    T = h.sum()
+    cs2 = 1 / 3
+    om = 1.3
+    out = orc.collide_h_node(h, T, ux, uy, om)
+    c10, c01 = _central(h, ex, ey, ux, uy, 1, 0), _central(h, ex, ey, ux, uy, 0, 1)
+    want = {(0, 0): T, (1, 0): (1 - om) * c10, (0, 1): (1 - om) * c01, (2, 0): T * cs2, (0, 2): T * cs2,
+            (1, 1): 0.0, (2, 1): 0.0, (1, 2): 0.0, (2, 2): T * cs2 * cs2}
+    for k, v in want.items():
+        assert abs(_central(out, ex, ey, ux, uy, *k) - v) < 1e-15, k

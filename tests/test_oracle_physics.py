@@ -294,3 +294,41 @@ def test_two_layer_startup_decays_at_the_closed_form_rate():
     d2 = np.max(np.abs(us[7] - us[6]))
     lam = -math.log(d2 / d1) / 1000.0
     assert lam == pytest.approx(lam0, rel=3e-2)
+
+
+@pytest.mark.parametrize("sigma_T,sigma_TT", [(-2e-4, 0.0), (-1e-4, 3e-4)])
+def test_wall_rows_see_the_dirichlet_temperature_ghosts(sigma_T, sigma_TT):
+    # Secs. 3 and 5: a vertical stripe of fluid b (interfaces normal to x,
+    # meeting both walls) in a temperature field linear in y between walls at
+    # T_h and T_c (dT = 0), initialised at equilibrium at rest.  Then j = 0 and
+    # the first velocity is u = F_t / (2 rho) (Sec. 4.2), so u_y is the
+    # Marangoni force 1.5 W |grad phi|^2 d(sigma)/dy / (2 rho) on each row.
+    # With T linear in y, the stencil's central difference of the quadratic
+    # sigma(T) is exact, so d(sigma)/dy = sigma'(T(j)) dT/dy on every row --
+    # on the wall rows only if the ghost rows carry T_ghost = 2 T_wall - T
+    # (a mirrored ghost halves the wall-row force).  Checked row by row
+    # against sigma'(T(j)) = sigma_T + 2 sigma_TT (T(j) - T_ref).
+    nx, ny = 32, 16
+    c = inputs.cfg(nx=nx, ny=ny, b=8.0, dT=0.0, T_h=1.6, T_c=0.4, sigma_T=sigma_T, sigma_TT=sigma_TT)
+    x = np.arange(nx, dtype=float)
+    W = c["W"]
+    stripe = 0.5 * (np.tanh(2 * (x - 9.5) / W) - np.tanh(2 * (x - 22.5) / W))
+    phi = np.tile(stripe, (ny, 1))
+    j = np.arange(ny, dtype=float)
+    T = np.tile((c["T_h"] + (c["T_c"] - c["T_h"]) * (j + 0.5) / ny)[:, None], (1, nx))
+    zero = np.zeros((ny, nx))
+    o = orc.Oracle(c)
+    o.init_fields(phi, zero, zero, T)
+    F = o.fields()
+    dsig = c["sigma_T"] + 2 * c["sigma_TT"] * (T[:, 0] - c["T_ref"])
+    # per column the ratio u_y(j) / sigma'(T(j)) is the same on every row
+    col = int(np.argmax(np.abs(F["uy"][ny // 2])))
+    ratio = F["uy"][:, col] / dsig
+    assert np.max(np.abs(ratio - ratio[ny // 2])) <= 1e-12 * abs(ratio[ny // 2])
+    assert np.max(np.abs(F["uy"][0] / dsig[0] - F["uy"][ny // 2] / dsig[ny // 2])) <= 1e-12 * np.max(np.abs(ratio))
+    assert np.max(np.abs(F["uy"][ny - 1] / dsig[ny - 1] - F["uy"][ny // 2] / dsig[ny // 2])) <= 1e-12 * np.max(np.abs(ratio))
+    # and its size is the force of the definition: the isotropic x-derivative
+    # of an x-only field is its central difference
+    gx = (np.roll(stripe, -1) - np.roll(stripe, 1)) / 2
+    want = 1.5 * W * gx ** 2 * dsig[ny // 2] * (c["T_c"] - c["T_h"]) / ny / 2.0
+    assert np.max(np.abs(F["uy"][ny // 2] - want)) <= 1e-12 * np.max(np.abs(want))
