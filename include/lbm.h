@@ -137,6 +137,19 @@ int lbm_residual(lbm_ctx* ctx, int32_t inst, double* r, double* sum_phi, double*
  * the first step after init.  Synchronises. */
 int lbm_retire(lbm_ctx* ctx, int32_t inst);
 
+/* Start instance inst again from fields, at any step, leaving the other
+ * instances untouched: its populations are set to the equilibrium of the
+ * fields exactly as lbm_init sets them (fields NULL: the cold start from
+ * rest), its residual history and retirement are cleared and it takes part
+ * in later steps and solves again.  fields: host arrays phi, ux, uy, T of
+ * this instance ([ny][nx] each, concatenated).  The instance's reported step
+ * count keeps counting from the context's steps (so a restart after a
+ * divergence is charged the steps already spent).  This is the fallback of
+ * a warm-started solve: a channel whose start diverged (LBM_EDIVERGED) is
+ * restarted from rest.  LBM_EINVAL for a bad index or a non-finite field
+ * value, LBM_ESTATE before lbm_init.  Synchronises. */
+int lbm_restart(lbm_ctx* ctx, int32_t inst, const double* fields);
+
 /* Raw populations of instance inst, float64 [3][9][ny][nx] (host).  Syncs. */
 int lbm_get_state(lbm_ctx* ctx, int32_t inst, double* pop);
 /* Overwrite instance inst with populations (host, float64 [3][9][ny][nx]). */

@@ -21,7 +21,7 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 
 # Every function declared in include/lbm.h.
 EXPORTS = ("lbm_create", "lbm_init", "lbm_init_device", "lbm_step", "lbm_solve", "lbm_fields", "lbm_residual",
-           "lbm_get_state", "lbm_set_state", "lbm_retire", "lbm_profile_steps", "lbm_set_tile", "lbm_autotune",
+           "lbm_get_state", "lbm_set_state", "lbm_retire", "lbm_restart", "lbm_profile_steps", "lbm_set_tile", "lbm_autotune",
            "lbm_info",
            "lbm_destroy", "lbm_strerror")
 
@@ -79,6 +79,7 @@ def load():
     L.lbm_profile_steps.argtypes = [vp, ctypes.c_int64, dp]
     L.lbm_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.lbm_retire.argtypes = [vp, ctypes.c_int32]
+    L.lbm_restart.argtypes = [vp, ctypes.c_int32, dp]
     L.lbm_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                dp]
     L.lbm_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -275,6 +276,16 @@ def lbm_profile_steps(ctx: _Ctx, n: int) -> float:
 
 def lbm_retire(ctx: _Ctx, inst: int):
     _check(load().lbm_retire(ctx.h, int(inst)), "lbm_retire")
+
+
+def lbm_restart(ctx: _Ctx, inst: int, fields=None):
+    """Start channel inst again: from rest (fields None) or from (phi, ux, uy, T)."""
+    buf = None
+    if fields is not None:
+        ny, nx = ctx.shape(inst)
+        buf = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).reshape(ny * nx)
+                                                   for a in fields]))
+    _check(load().lbm_restart(ctx.h, int(inst), _dp(buf)), "lbm_restart")
 
 
 def lbm_set_tile(ctx: _Ctx, tx: int, ty: int):

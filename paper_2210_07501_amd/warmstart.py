@@ -296,7 +296,15 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
     lbm_set_state, exact), which finishes them within the remaining cap, and
     are retired from the float32 context with the finished state written
     back.  Their records then hold the float64 residual, the total steps and
-    "finished_fp64": True."""
+    "finished_fp64": True.
+
+    Fallback: a channel whose state turns non-finite (a diverged warm start,
+    a prediction with non-finite values) is retired by the residual check
+    with LBM_EDIVERGED; it is started again from rest in the same context
+    (lbm_restart), once, and its record carries "restarted_cold": True and
+    the steps it has taken in all (those spent before the divergence
+    included).  A channel that diverges again from rest stays retired and
+    is reported with "diverged": True."""
     t0 = time.perf_counter() if t0 is None else t0
     n = len(cfgs)
     watch = finish_fp64 and precision == lbm.LBM_FP32_DEV
@@ -311,7 +319,9 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
         c64 = lbm.lbm_create([cfgs[k] for k in todo], precision=lbm.LBM_FP64)
         for q, k in enumerate(todo):
             lbm.lbm_set_state(c64, q, lbm.lbm_get_state(ctx, k))
-        lbm.lbm_solve(c64, tol, cap - done)
+        rc64, _ = lbm.lbm_solve(c64, tol, cap - done)
+        if rc64 not in (lbm.LBM_OK, lbm.LBM_EDIVERGED):
+            raise lbm.LBMError(rc64, "lbm_solve (float64 finish)")
         for q, k in enumerate(todo):
             r64 = lbm.lbm_residual(c64, q)
             lbm.lbm_set_state(ctx, k, lbm.lbm_get_state(c64, q))
@@ -321,14 +331,32 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
             finished[k] = r64
         lbm.lbm_destroy(c64)
 
+    restarted = set()
+    first = True
     while done < cap:
-        step = min(chunk, cap - done)
+        # a short first solve catches a start that diverges at once (a bad
+        # prediction) before a whole chunk goes by
+        step = min(1000 if first else chunk, cap - done)
         rc, active = lbm.lbm_solve(ctx, tol, step)
         done += step
+        if rc == lbm.LBM_EDIVERGED:
+            bad = [k for k in range(n) if k not in restarted and k not in finished
+                   and lbm.lbm_residual(ctx, k)["diverged"]]
+            for k in bad:
+                lbm.lbm_restart(ctx, k)          # the cold start from rest
+                restarted.add(k)
+            active += len(bad)
+            if verbose and bad:
+                log("  solve: %d channel(s) diverged, restarted from rest: %s" % (len(bad), bad))
+        elif rc != lbm.LBM_OK:
+            raise lbm.LBMError(rc, "lbm_solve")
         if verbose:
             log("  solve: %d steps, %d of %d active, %.1f s" % (done, active, n, time.perf_counter() - t0))
         if active == 0:
             break
+        if first:
+            first = False
+            continue
         if watch:
             res = [lbm.lbm_residual(ctx, k) for k in range(n)]
             hist.append([r["r"] for r in res])
@@ -340,6 +368,8 @@ def run_to_tolerance(ctx, cfgs, precision, tol=1e-8, cap=400_000, chunk=50_000, 
     res = [lbm.lbm_residual(ctx, k) for k in range(n)]
     for k, r in finished.items():
         res[k] = r
+    for k in range(n):
+        res[k]["restarted_cold"] = k in restarted
     return res
 
 
