@@ -46,7 +46,7 @@ struct lbm_ctx {
     void* phir = nullptr;              // zeroth moment of the streamed reference populations minus phi0, by row
     void* fq = nullptr;                // flux reference of f (half its y-moment) by row
     void* fr = nullptr;                // constant part of the stored post-collision y-moment of f by row
-    void* twall = nullptr;             // bottom-wall temperature by column
+    double* twall = nullptr;           // bottom-wall temperature by column (float64 in both precisions)
     float* tref = nullptr;             // per-node temperature reference (float32 mode)
     float* tref_new = nullptr;         // references written by a check step
     int32_t* dl = nullptr;             // per-node phi-reference offsets, units of DL_Q (float32 mode)
@@ -386,7 +386,10 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         I.T_h = p.T_h; I.dT = p.dT; I.T_c = p.T_c;
         I.kx = 2.0 * M_PI / ((double)p.nx / (double)p.n_waves);
         I.Fx = p.Fx_ext; I.Fy = p.Fy_ext;
-        I.p_r = precision == LBM_FP64 ? 0.0 : 1.0 / 3.0;
+        // storage reference of g: the rest pressure 1/3, rounded to a float
+        // value so that the float32 kernel and the float64 set-up code use
+        // the very same number
+        I.p_r = precision == LBM_FP64 ? 0.0 : (double)(float)(1.0 / 3.0);
         const long long n = (long long)p.nx * p.ny;
         pop += 27 * n;
         nodes += n;
@@ -416,7 +419,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->phir = dev_alloc(c, (size_t)rows * c->elem);
     c->fq = dev_alloc(c, (size_t)rows * c->elem);
     c->fr = dev_alloc(c, (size_t)rows * c->elem);
-    c->twall = dev_alloc(c, (size_t)cols * c->elem);
+    c->twall = (double*)dev_alloc(c, (size_t)cols * sizeof(double));
     if (precision == LBM_FP32_DEV) {
         c->tref = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
         c->tref_new = (float*)dev_alloc(c, (size_t)nodes * sizeof(float));
@@ -478,8 +481,11 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
                 double* qr = &tr[c->h_inst[k].row_off + 2];
                 double* qq = &tq[c->h_inst[k].row_off + 2];
                 double* qf = &tf[c->h_inst[k].row_off + 2];
-                for (int j = -2; j <= ny + 1; ++j)
+                for (int j = 0; j < ny; ++j)
                     q0[j] = (double)(float)(0.5 * (1.0 + std::tanh(2.0 * ((p.b - 0.5) - (double)j) / p.W)));
+                // ghost rows mirror the rows next to the walls, as phi does
+                q0[-1] = q0[0]; q0[-2] = q0[1];
+                q0[ny] = q0[ny - 1]; q0[ny + 1] = q0[ny - 2];
                 std::vector<double> r01(ny);
                 for (int j = 0; j < ny; ++j) {
                     double s0 = 0.0, s1 = 0.0;
@@ -547,7 +553,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
                 qq[ny] = -qq[ny - 1];
                 for (int j = 0; j < ny; ++j) {
                     // reference theta0, n0y as the step kernel forms them
-                    // (tanh continuation into the ghost rows)
+                    // (mirrored ghost rows)
                     const double fq_sum = qq[j - 1] + qq[j + 1];
                     const double rest = mth(q0[j], 0.5 * (q0[j + 1] - q0[j - 1]));
                     qf[j] = (double)(float)((1.0 - w) * (r01[j] + fq_sum) + w * rest - 2.0 * qq[j]);
@@ -583,14 +589,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
                 td[c->h_inst[k].col_off + i] = p.T_h + p.dT * std::cos(2.0 * M_PI * (double)i / l);
         }
         hipError_t e;
-        if (precision == LBM_FP64) {
-            e = hipMemcpyAsync(c->twall, td.data(), cols * sizeof(double), hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        } else {
-            std::vector<float> tf(td.begin(), td.end());
-            e = hipMemcpyAsync(c->twall, tf.data(), cols * sizeof(float), hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        }
+        e = hipMemcpyAsync(c->twall, td.data(), cols * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) rc = fail_hip(c, e, "upload wall temperatures");
     }
     if (rc == LBM_OK) rc = build_tiles(c, true);
@@ -661,6 +661,7 @@ static int init_impl(lbm_ctx* c, const double* fields, bool device) {
     a.tref = c->tref;
     a.dl = c->dl;
     a.cold = fields ? 0 : 1;
+    a.field_base = 0;
     double* dfields = nullptr;
     if (fields) {
         if (!device)
@@ -788,6 +789,56 @@ int lbm_retire(lbm_ctx* c, int32_t inst) {
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->retired[inst] = 1;
+    rc = build_tiles(c, false);
+    if (rc) return rc;
+    return upload_tables(c);
+}
+
+int lbm_restart(lbm_ctx* c, int32_t inst, const double* fields) {
+    if (!c || inst < 0 || inst >= c->n_inst) return LBM_EINVAL;
+    if (!c->initialised) return LBM_ESTATE;
+    const long long n = (long long)c->params[inst].nx * c->params[inst].ny;
+    if (fields)
+        for (long long q = 0; q < 4 * n; ++q)
+            if (!std::isfinite(fields[q])) return LBM_EINVAL;
+    // bring the host's retirement flags up to date, then take this channel
+    // back into the launches with a fresh residual history
+    std::vector<Result> res;
+    int rc = refresh_results(c, res);
+    if (rc) return rc;
+    const Inst& I = c->h_inst[inst];
+    InitArgs a;
+    a.insts = c->d_inst + inst;                   // one instance: blockIdx.y == 0
+    a.dst_v = (c->steps & 1) ? c->popB : c->popA; // the buffer the next step gathers from
+    a.phi0_v = c->phi0;
+    a.fq_v = c->fq;
+    a.tw_v = c->twall;
+    a.tref = c->tref;
+    a.dl = c->dl;
+    a.cold = fields ? 0 : 1;
+    a.field_base = I.node_off;
+    double* dfields = nullptr;
+    for (int f = 0; f < 4; ++f) a.fields[f] = nullptr;
+    if (fields) {
+        dfields = (double*)dev_alloc(c, sizeof(double) * 4 * n);
+        if (!dfields) return LBM_ENOMEM;
+        HIPCHK(c, hipMemcpyAsync(dfields, fields, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream));
+        for (int f = 0; f < 4; ++f) a.fields[f] = dfields + f * n;
+    }
+    const Result zero{};
+    const int one = 1;
+    HIPCHK(c, hipMemcpyAsync(c->d_res + inst, &zero, sizeof(Result), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char*)(c->d_inst + inst) + offsetof(Inst, active), &one, sizeof(int),
+                             hipMemcpyHostToDevice, c->stream));
+    hipError_t e = launch_init(c->prec, a, (int)n, 1, c->stream);
+    if (e != hipSuccess) return fail_hip(c, e, "init kernel launch");
+    if (c->prec == LBM_FP32_DEV) {
+        e = launch_dl_flags(c->d_inst, c->dl, c->dlz, c->max_chunks, c->n_inst, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "offset flag launch");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dfields) dev_release(c, dfields);
+    c->retired[inst] = 0;
     rc = build_tiles(c, false);
     if (rc) return rc;
     return upload_tables(c);

@@ -59,7 +59,7 @@ struct StepArgs {
     const void* src_v;
     void* dst_v;
     const void* phi0_v;           // reference rows (compute type)
-    const void* tw_v;             // bottom-wall temperature by column (compute type)
+    const void* tw_v;             // bottom-wall temperature by column (float64)
     const void* phir_v;           // zeroth moment of the streamed reference populations minus phi0, by row
     const void* fq_v;             // flux reference: half the reference y-moment of f, by row
     const void* fr_v;             // constant part of the stored post-collision y-moment of f, by row
@@ -91,6 +91,7 @@ struct InitArgs {
     float* tref;
     int32_t* dl;                  // phi-reference offsets, units of DL_Q (float32 mode)
     const double* fields[4];      // phi, ux, uy, T (device), when not cold
+    long long field_base;         // node offset of the first node the field arrays hold
     int cold;
 };
 

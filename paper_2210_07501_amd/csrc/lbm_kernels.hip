@@ -63,6 +63,7 @@ template <class R> struct P {
     R W, inv_W, M, w_phi, drho, rho_a, mu_a, dmu, k_a, dk;
     R s0, sT, sTT, Tsig;   // Tsig: T_ref of the surface-tension law
     R T_h, dT, T_c, kx, Fx, Fy, p_r;
+    double T_top;         // top-wall temperature, kept in float64 for the wall scheme
     __device__ void load(const Inst& I) {
         nx = I.nx; ny = I.ny;
         W = R(I.W); inv_W = R(1.0 / I.W); M = R(I.M_phi); w_phi = R(I.w_phi);
@@ -70,7 +71,7 @@ template <class R> struct P {
         mu_a = R(I.mu_a); dmu = R(I.mu_b - I.mu_a);
         k_a = R(I.k_a); dk = R(I.k_b - I.k_a);
         s0 = R(I.s0); sT = R(I.sT); sTT = R(I.sTT); Tsig = R(I.T_ref);
-        T_h = R(I.T_h); dT = R(I.dT); T_c = R(I.T_c); kx = R(I.kx);
+        T_h = R(I.T_h); dT = R(I.dT); T_c = R(I.T_c); kx = R(I.kx); T_top = I.T_c;
         Fx = R(I.Fx); Fy = R(I.Fy); p_r = R(I.p_r);
     }
 };
@@ -182,9 +183,11 @@ template <class S> struct Pop {
 // bounce-back, h anti-bounce-back to the wall temperature, f specular
 // (free-slip).  Returned as deviations relative to the references of node
 // (i, j): phi0 of row j, p_r, and Tro, the node's own temperature reference.
-// NEED: bit 0 f, bit 1 g, bit 2 h.  tw: bottom-wall temperature by column.
+// NEED: bit 0 f, bit 1 g, bit 2 h.  tw: bottom-wall temperature by column
+// (float64 in both precisions: the wall value of the anti-bounce-back is a
+// boundary condition, not a deviation, and is formed before rounding).
 template <class S, class R, int NEED>
-__device__ __forceinline__ void pull_node(const Pop<S>& src, const R* __restrict__ tw, const P<R>& p, int i,
+__device__ __forceinline__ void pull_node(const Pop<S>& src, const double* __restrict__ tw, const P<R>& p, int i,
                                           int j, R Tro, R* f, R* g, R* h) {
     const int nx = p.nx, ny = p.ny;
     const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
@@ -208,8 +211,8 @@ __device__ __forceinline__ void pull_node(const Pop<S>& src, const R* __restrict
                 if (NEED & 1) f[a] = R(src.ld(0, MIRY(a), o0));
                 if (NEED & 2) g[a] = R(src.ld(1, OPP(a), oi));
                 if (NEED & 4) {
-                    const R Tw = (ey > 0) ? tw[i] : p.T_c;
-                    h[a] = -R(src.ld(2, OPP(a), oi)) + R(2) * W9<R>::w(a) * (Tw - Tro);
+                    const double Tw = (ey > 0) ? tw[i] : p.T_top;
+                    h[a] = -R(src.ld(2, OPP(a), oi)) + R(2.0 * W9<double>::w(a) * (Tw - (double)Tro));
                 }
             }
         }
@@ -260,7 +263,7 @@ void step_kernel(StepArgs a) {
     constexpr int LX1 = TX + 2, LY1 = TY + 2;   // T, p*, n region (halo 1)
     constexpr int RING = LX2 * LY2 - TX * TY;
 
-    __shared__ R s_phb[LY2 * LX2];  // phi - phi0(row)
+    __shared__ R s_phd[LY2 * LX2];  // phi - phi0(row) - dl DL_Q (the node's own reference; dl = 0 in float64 mode)
     __shared__ R s_Tr[LY2 * LX2];   // temperature reference (float32 mode)
     constexpr int LX3 = TX + 6, LY3 = TY + 6;   // phi-reference offset region (halo 3)
     __shared__ int32_t s_dl[DEV ? LY3 * LX3 : 1];   // phi reference minus phi0(row), units of DL_Q
@@ -305,7 +308,7 @@ void step_kernel(StepArgs a) {
     const int x0 = tcol * TX, y0 = trow * TY;
 
     Pop<S> src{(S*)a.src_v + I.pop_off, (uint32_t)nx};
-    const R* __restrict__ tw = (const R*)a.tw_v + I.col_off;
+    const double* __restrict__ tw = (const double*)a.tw_v + I.col_off;
     const int tid = threadIdx.x;
     auto colwrap = [&](int ii) {
         ii = ii < 0 ? ii + nx : ii;
@@ -352,7 +355,11 @@ void step_kernel(StepArgs a) {
             const int jj = y0 + hy;
             const bool in = jj >= 0 && jj < ny;
             const uint32_t o = in ? (uint32_t)jj * (uint32_t)nx + (uint32_t)colwrap(x0 + hx) : 0u;
-            s_dl[k] = (in && !dz) ? dlv[o] : 0;
+            // ghost rows take the offsets of their mirror rows (phi is mirrored
+            // at the walls); the pull corrections never read ghost rows
+            const int jm = jj < 0 ? -1 - jj : (jj >= ny ? 2 * ny - 1 - jj : jj);
+            const uint32_t om = (jm >= 0 && jm < ny) ? (uint32_t)jm * (uint32_t)nx + (uint32_t)colwrap(x0 + hx) : 0u;
+            s_dl[k] = (jm >= 0 && jm < ny && !dz) ? dlv[om] : 0;
             if (hy >= -2 && hy <= TY + 1 && hx >= -2 && hx <= TX + 1)
                 s_Tr[(hy + 2) * LX2 + hx + 2] = in ? tref[o] : R(0);
         }
@@ -400,6 +407,19 @@ void step_kernel(StepArgs a) {
         }
     };
 
+    // float32 mode: phi of a halo node relative to its own reference
+    // phi0(row) + dl DL_Q, summed in float64 (the row constants dR and the flux
+    // reference are not small, their rounding would vary along x)
+    auto ring_phd = [&](const R* tf, int hx, int hy, int jj) -> R {
+        int i0, ix, iy;
+        fcorr(hx, hy, jj, i0, ix, iy);
+        const int dln = dz ? 0 : s_dl[(hy + 3) * LX3 + hx + 3];
+        double sd = (double)s_dR[hy + 2] + ((double)s_fq[hy + 2] - (double)s_fq[hy + 4]) + (double)(i0 - 36 * dln) * DL_U;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sd += (double)tf[q];
+        return (R)sd;
+    };
+
     // ---- phase 1: pull own node and the halo ring ---------------------------
     const int tx = tid % TX, ty = tid / TX;
     const int gi = (x0 + tx < nx) ? x0 + tx : modx(x0 + tx, nx), gj = y0 + ty;
@@ -433,7 +453,11 @@ void step_kernel(StepArgs a) {
             for (int q = 0; q < 9; ++q) dph_d += (double)f[q];
             rf[0] = (R)dph_d;
         }
-        s_phb[(ty + 2) * LX2 + tx + 2] = rf[0];
+        // LDS keeps phi relative to the node's own reference phi0(row) + dl:
+        // tiny near a steady state, so the small variations of phi along the
+        // interface survive float32; stencils add the references' share from
+        // the integer offsets, exactly
+        s_phd[(ty + 2) * LX2 + tx + 2] = DEV ? (R)(dph_d - (double)s_dl[(ty + 3) * LX3 + tx + 3] * DL_Q) : rf[0];
         s_pb[(ty + 1) * LX1 + tx + 1] = rg[0];
         s_Tb[(ty + 1) * LX1 + tx + 1] = rh[0];
     }
@@ -457,11 +481,9 @@ void step_kernel(StepArgs a) {
                 R c0, cx, cy;
                 tcorr(hx, hy, jj, c0, cx, cy);
                 s3 += c0;
-                int i0, ix, iy;
-                fcorr(hx, hy, jj, i0, ix, iy);
-                s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]) + (R)((double)i0 * DL_U);
+                s1 = ring_phd(tf, hx, hy, jj);
             }
-            s_phb[(hy + 2) * LX2 + hx + 2] = s1;
+            s_phd[(hy + 2) * LX2 + hx + 2] = s1;
             s_pb[(hy + 1) * LX1 + hx + 1] = s2;
             s_Tb[(hy + 1) * LX1 + hx + 1] = s3;
         } else {
@@ -469,12 +491,8 @@ void step_kernel(StepArgs a) {
             R s1 = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) s1 += tf[q];
-            if (DEV) {
-                int i0, ix, iy;
-                fcorr(hx, hy, jj, i0, ix, iy);
-                s1 += s_dR[hy + 2] + (s_fq[hy + 2] - s_fq[hy + 4]) + (R)((double)i0 * DL_U);
-            }
-            s_phb[(hy + 2) * LX2 + hx + 2] = s1;
+            if (DEV) s1 = ring_phd(tf, hx, hy, jj);
+            s_phd[(hy + 2) * LX2 + hx + 2] = s1;
         }
     }
     __syncthreads();
@@ -488,15 +506,16 @@ void step_kernel(StepArgs a) {
         const int mhy = mj - y0;
         const bool valid = (jj >= -2 && jj <= ny + 1) && mhy >= -2 && mhy <= TY + 1;
         R v = R(0);
-        if (valid) v = s_phb[(mhy + 2) * LX2 + hx + 2] + (s_phi0[mhy + 2] - s_phi0[hy + 2]);
-        s_phb[k] = v;
+        // phi0 and the offsets are mirrored in the ghost rows too
+        if (valid) v = s_phd[(mhy + 2) * LX2 + hx + 2];
+        s_phd[k] = v;
         if (hx >= -1 && hx <= TX && hy >= -1 && hy <= TY) {
             R vp = R(0), vT = R(0), vr = R(0);
             if (valid && (jj == -1 || jj == ny)) {
                 vp = s_pb[(mhy + 1) * LX1 + hx + 1];
                 const R Tm = s_Tb[(mhy + 1) * LX1 + hx + 1];
                 vr = DEV ? s_Tr[(mhy + 2) * LX2 + hx + 2] : R(0);   // ghost reference := mirror's
-                const R Tw = (jj < 0) ? tw[colwrap(x0 + hx)] : p.T_c;
+                const double Tw = (jj < 0) ? tw[colwrap(x0 + hx)] : p.T_top;
                 // T_ghost = 2 T_w - T_mirror; deviation from vr formed exactly
                 vT = R(2.0 * ((double)Tw - (double)vr)) - Tm;
             }
@@ -506,6 +525,24 @@ void step_kernel(StepArgs a) {
         }
     }
     __syncthreads();
+
+    // Isotropic gradient of phi - phi0(row) at halo position (hx, hy): the
+    // stencil of the LDS deviations plus that of the reference offsets,
+    // taken in integers (exact) and scaled once.
+    auto grad_phi = [&](int hx, int hy, R& gx, R& gy) {
+        const R* v = &s_phd[(hy + 2) * LX2 + hx + 2];
+        const R E = v[1], Wv = v[-1], N = v[LX2], Sv = v[-LX2];
+        const R NE = v[LX2 + 1], NW = v[LX2 - 1], SE = v[-LX2 + 1], SW = v[-LX2 - 1];
+        gx = (E - Wv) * (R(1) / R(3)) + (NE - NW + SE - SW) * (R(1) / R(12));
+        gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12));
+        if (DEV && !dz) {
+            const int32_t* d = &s_dl[(hy + 3) * LX3 + hx + 3];
+            const int sx = 4 * (d[1] - d[-1]) + (d[LX3 + 1] - d[LX3 - 1] + d[-LX3 + 1] - d[-LX3 - 1]);
+            const int sy = 4 * (d[LX3] - d[-LX3]) + (d[LX3 + 1] + d[LX3 - 1] - d[-LX3 + 1] - d[-LX3 - 1]);
+            gx += R(sx) * R(DL_Q / 12.0);
+            gy += R(sy) * R(DL_Q / 12.0);
+        }
+    };
 
     // ---- phase 2: interface normal on the tile + 1 ring ----------------------
     // n = grad phi / sqrt(|grad phi|^2 + eps^2); stored as n_x and the
@@ -518,11 +555,8 @@ void step_kernel(StepArgs a) {
         const int jj = y0 + hy;
         R nxv = R(0), dny = R(0);
         if (jj >= -1 && jj <= ny) {
-            const R* c = &s_phb[(hy + 2) * LX2 + hx + 2];
-            const R E = c[1], Wv = c[-1], N = c[LX2], Sv = c[-LX2];
-            const R NE = c[LX2 + 1], NW = c[LX2 - 1], SE = c[-LX2 + 1], SW = c[-LX2 - 1];
-            const R Gx = (E - Wv) * (R(1) / R(3)) + (NE - NW + SE - SW) * (R(1) / R(12));
-            const R gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12));
+            R Gx, gy;
+            grad_phi(hx, hy, Gx, gy);
             const R G0y = R(0.5) * (s_phi0[hy + 3] - s_phi0[hy + 1]);
             const R Gy = gy + G0y;
             const R eps2 = R(EPS_N * EPS_N);
@@ -558,7 +592,7 @@ void step_kernel(StepArgs a) {
             gy = (N - Sv) * (R(1) / R(3)) + (NE + NW - SE - SW) * (R(1) / R(12));
         };
         R Gx, Gy;
-        grad(s_phb, c2, LX2, Gx, Gy);
+        grad_phi(tx, ty, Gx, Gy);
         Gy += R(0.5) * (s_phi0[ty + 3] - s_phi0[ty + 1]);
         const R g2 = Gx * Gx + Gy * Gy;
         const R nxv = s_nx[c1];
@@ -596,13 +630,23 @@ void step_kernel(StepArgs a) {
         // pressure force F_p = -grad(p* - rho c_s^2), rho linear in phi
         const R Fpx = -dpx + cs2 * p.drho * Gx;
         const R Fpy = -dpy + cs2 * p.drho * Gy;
-        // macroscopic update (Sec. 4.2)
+        // macroscopic update (Sec. 4.2).  rho is formed in float64 from phi
+        // in float64: it enters p - rho c_s^2 of the g equilibrium, whose
+        // float32 rounding would otherwise be re-applied to the momentum at
+        // every step (float32 mode; in float64 mode these are the same values)
         const R phb = rf[0];
         const R phi = s_phi0[ty + 2] + phb;
-        const R rho = p.rho_a + phi * p.drho;
+        const double phi_d = DEV ? (double)s_phi0[ty + 2] + dph_d : (double)phi;
+        const double rho_d = (double)p.rho_a + phi_d * (double)p.drho;
+        const R rho = (R)rho_d;
         const R rrho = rcp(rho);
-        const R ux = (rg[3] + R(0.5) * cs2 * Ftx) * (R(3) * rrho);
-        const R uy = (rg[1] + R(0.5) * cs2 * Fty) * (R(3) * rrho);
+        // u in float64 as well: the g collision turns it back into momentum,
+        // so a rounded 1/rho would bias the momentum at every step where
+        // rho != 1
+        const double rrho_d = 1.0 / rho_d;
+        const double ux_d = ((double)rg[3] + 0.5 * (1.0 / 3.0) * (double)Ftx) * (3.0 * rrho_d);
+        const double uy_d = ((double)rg[1] + 0.5 * (1.0 / 3.0) * (double)Fty) * (3.0 * rrho_d);
+        const R ux = (R)ux_d, uy = (R)uy_d;
         const R Gam = Fpx * ux + Fpy * uy;
         const R pb = rg[0] + R(0.5) * Gam;          // p - p_r
         R Tb = rh[0];                                // T - Tro
@@ -610,7 +654,7 @@ void step_kernel(StepArgs a) {
         if (MODE == 2) {
             if (own_ok) {
                 const size_t q = (size_t)I.node_off + (size_t)gj * nx + gi;
-                a.out[0][q] = (double)phi;
+                a.out[0][q] = phi_d;
                 a.out[1][q] = (double)ux;
                 a.out[2][q] = (double)uy;
                 a.out[3][q] = (double)Tro + (double)Tb;
@@ -629,15 +673,15 @@ void step_kernel(StepArgs a) {
                     red[1] = dux * dux + duy * duy;
                     red[2] = (Tfull - o_T) * (Tfull - o_T);
                     red[3] = dT * dT;
-                    red[4] = (double)phi;
-                    red[5] = (double)rho;
+                    red[4] = phi_d;
+                    red[5] = rho_d;
                     const bool bad = !(isfinite(dux) && isfinite(duy) && isfinite(Tfull) &&
-                                       isfinite((double)phi) && isfinite((double)pb));
+                                       isfinite(phi_d) && isfinite((double)pb));
                     red[6] = bad ? 1.0 : 0.0;
                     a.snap[0][q] = dux;
                     a.snap[1][q] = duy;
                     a.snap[2][q] = Tfull;
-                    a.snap[3][q] = (double)phi;
+                    a.snap[3][q] = phi_d;
                 }
                 if (DEV) {
                     // move this node's temperature reference to its current
@@ -748,37 +792,50 @@ void step_kernel(StepArgs a) {
                 raw_to_dist(c, h);
             }
             // --- hydrodynamics (Sec. 4.2), stored as g - w p_r ---
+            // computed in float64 in both precisions: in float32 its rounding,
+            // relative to the O(1) pressure terms, dominates the velocity error
             {
-                const R pr = p.p_r;
-                const R vphi = pb + (pr - rho * cs2);     // p - rho c_s^2
-                const R P0 = rg[0] + pr;                  // sum g (full)
+                using D = double;
+                const D cs2d = 1.0 / 3.0;
+                const D uxd = ux_d, uyd = uy_d, wn = w_nu;
+                const D ux2 = uxd * uxd, uy2 = uyd * uyd, uxy = uxd * uyd;
+                const D Fpxd = Fpx, Fpyd = Fpy;
+                const D Gd = Fpxd * uxd + Fpyd * uyd;     // Gamma = F_p . u
+                const D pbd = (D)rg[0] + 0.5 * Gd;         // p - p_r
+                const D pr = (D)p.p_r;
+                const D vphi = pbd + (pr - rho_d * cs2d);   // p - rho c_s^2
+                const D P0 = (D)rg[0] + pr;                 // sum g (full)
+                const D r1 = rg[1], r2 = rg[2], r3 = rg[3], r4 = rg[4], r6 = rg[6];
                 // pre-collision central moments that relax at omega_nu
-                const R e2d = (rg[6] - rg[2]) - R(2) * ux * rg[3] + R(2) * uy * rg[1] + (ux2 - uy2) * P0;
-                const R e11 = rg[4] - uy * rg[3] - ux * rg[1] + uxy * P0;
+                const D e2d = (r6 - r2) - 2.0 * uxd * r3 + 2.0 * uyd * r1 + (ux2 - uy2) * P0;
+                const D e11 = r4 - uyd * r3 - uxd * r1 + uxy * P0;
                 // sources (Sec. 4.2)
-                const R s10 = cs2 * Ftx - ux * Gam, s01 = cs2 * Fty - uy * Gam;
-                const R s20 = R(2) * cs2 * Fpx * ux + (ux2 + cs2) * Gam;
-                const R s02 = R(2) * cs2 * Fpy * uy + (uy2 + cs2) * Gam;
-                const R s11 = cs2 * (Fpx * uy + Fpy * ux) + uxy * Gam;
-                const R q2d = vphi * (ux2 - uy2), q11 = vphi * uxy;
-                const R t2d = e2d + w_nu * (q2d - e2d) + (R(1) - R(0.5) * w_nu) * (s20 - s02);
-                const R t11 = e11 + w_nu * (q11 - e11) + (R(1) - R(0.5) * w_nu) * s11;
+                const D s10 = cs2d * (D)Ftx - uxd * Gd, s01 = cs2d * (D)Fty - uyd * Gd;
+                const D s20 = 2.0 * cs2d * Fpxd * uxd + (ux2 + cs2d) * Gd;
+                const D s02 = 2.0 * cs2d * Fpyd * uyd + (uy2 + cs2d) * Gd;
+                const D s11 = cs2d * (Fpxd * uyd + Fpyd * uxd) + uxy * Gd;
+                const D q2d = vphi * (ux2 - uy2), q11 = vphi * uxy;
+                const D t2d = e2d + wn * (q2d - e2d) + (1.0 - 0.5 * wn) * (s20 - s02);
+                const D t11 = e11 + wn * (q11 - e11) + (1.0 - 0.5 * wn) * s11;
                 // trace: 2 p c_s^2 + vphi u^2 + s_2s / 2, minus p_r (2 c_s^2 + u^2)
-                const R t2s_dev = R(2) * cs2 * pb + (vphi - pr) * (ux2 + uy2) + R(0.5) * (s20 + s02);
-                const R t2d_dev = t2d - pr * (ux2 - uy2);
-                const R pv = pr - vphi;                   // p_r - (p - rho c_s^2)
-                R c[9];
-                c[0] = pb + R(0.5) * Gam;                           // 00
-                c[1] = pv * uy + R(0.5) * s01;                      // 01
-                c[2] = R(0.5) * (t2s_dev - t2d_dev);                // 02
-                c[3] = pv * ux + R(0.5) * s10;                      // 10
+                const D t2s_dev = 2.0 * cs2d * pbd + (vphi - pr) * (ux2 + uy2) + 0.5 * (s20 + s02);
+                const D t2d_dev = t2d - pr * (ux2 - uy2);
+                const D pv = pr - vphi;                    // p_r - (p - rho c_s^2)
+                D c[9];
+                c[0] = pbd + 0.5 * Gd;                              // 00
+                c[1] = pv * uyd + 0.5 * s01;                        // 01
+                c[2] = 0.5 * (t2s_dev - t2d_dev);                   // 02
+                c[3] = pv * uxd + 0.5 * s10;                        // 10
                 c[4] = t11 - pr * uxy;                              // 11
-                c[5] = pv * (uy2 + cs2) * ux;                       // 12
-                c[6] = R(0.5) * (t2s_dev + t2d_dev);                // 20
-                c[7] = pv * (ux2 + cs2) * uy;                       // 21
-                c[8] = pb * (cs2 * cs2) + (pb - rho * cs2) * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
-                central_to_raw(c, ux, uy);
-                raw_to_dist(c, g);
+                c[5] = pv * (uy2 + cs2d) * uxd;                     // 12
+                c[6] = 0.5 * (t2s_dev + t2d_dev);                   // 20
+                c[7] = pv * (ux2 + cs2d) * uyd;                     // 21
+                c[8] = pbd * (cs2d * cs2d) + (pbd - rho_d * cs2d) * (cs2d * (ux2 + uy2) + ux2 * uy2);  // 22
+                central_to_raw(c, uxd, uyd);
+                D go[9];
+                raw_to_dist(c, go);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) g[q] = (R)go[q];
             }
             if (own_ok) {
                 Pop<S> dst{(S*)a.dst_v + I.pop_off, (uint32_t)nx};
@@ -898,13 +955,12 @@ __global__ void count_active_kernel(const Inst* insts, int n, int* out) {
 // references are zero.
 
 // Temperature of node (i, j) from the init fields (cold start or given).
-template <class R>
-__device__ __forceinline__ double init_T_src(const InitArgs& a, const Inst& I, int i, int j, const R* tw) {
+__device__ __forceinline__ double init_T_src(const InitArgs& a, const Inst& I, int i, int j, const double* tw) {
     if (a.cold) {
         const double Tb = (double)tw[i];
         return Tb + (I.T_c - Tb) * ((double)j + 0.5) / (double)I.ny;
     }
-    return a.fields[3][(size_t)I.node_off + (size_t)j * I.nx + i];
+    return a.fields[3][(size_t)(I.node_off - a.field_base) + (size_t)j * I.nx + i];
 }
 
 // Equilibrium state from fields, written into the post-collision buffer so
@@ -920,7 +976,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const int i = (int)(q % nx), j = (int)(q / nx);
     const double cs2 = 1.0 / 3.0;
     // wall temperatures as the step kernel sees them
-    const R* twr = (const R*)a.tw_v + I.col_off;
+    const double* twr = (const double*)a.tw_v + I.col_off;
     auto tw_at = [&](int ii) { return (double)twr[ii]; };
     double phi, ux, uy;
     if (a.cold) {
@@ -929,7 +985,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         ux = 0.0;
         uy = 0.0;
     } else {
-        const size_t o = (size_t)I.node_off + (size_t)q;
+        const size_t o = (size_t)(I.node_off - a.field_base) + (size_t)q;
         phi = a.fields[0][o];
         ux = a.fields[1][o];
         uy = a.fields[2][o];
@@ -939,7 +995,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         const double Tb = tw_at(i);
         T = Tb + (I.T_c - Tb) * ((double)j + 0.5) / (double)ny;
     } else {
-        T = a.fields[3][(size_t)I.node_off + (size_t)q];
+        T = a.fields[3][(size_t)(I.node_off - a.field_base) + (size_t)q];
     }
     const double rho = I.rho_a + phi * (I.rho_b - I.rho_a);
     const double p0 = 1.0 / 3.0;
@@ -966,7 +1022,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
         if (!DEV) return 0;
         double ph;
         if (a.cold) ph = 0.5 * (1.0 + tanh(2.0 * ((I.b - 0.5) - (double)jj) / I.W));
-        else ph = a.fields[0][(size_t)I.node_off + (size_t)jj * I.nx + ii];
+        else ph = a.fields[0][(size_t)(I.node_off - a.field_base) + (size_t)jj * I.nx + ii];
         return (int32_t)llrint((ph - (double)phi0[jj]) / DL_Q);
     };
     auto dl_at = [&](int ii, int jj) { return (double)kdl_at(ii, jj) * DL_Q; };
@@ -1015,7 +1071,7 @@ __global__ __launch_bounds__(256) void state_kernel(StateArgs a) {
     const S* phi0 = (const S*)a.phi0_v + I.row_off + 2;
     const S* fq = (const S*)a.fq_v + I.row_off + 2;
     auto qf = [&](int kk, int r) { return (DEV && EX(kk) == 0 && EY(kk) != 0) ? EY(kk) * (double)fq[r] : 0.0; };
-    const S* tw = (const S*)a.tw_v + I.col_off;
+    const double* tw = (const double*)a.tw_v + I.col_off;
     const float* tref = a.tref ? a.tref + I.node_off : nullptr;
     const double pr = DEV ? I.p_r : 0.0;
     const double Tr_self = DEV ? (double)tref[q] : 0.0;

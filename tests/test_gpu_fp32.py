@@ -7,8 +7,9 @@ stated per quantity (relative max-norm of each distribution; u on the scale
 of the peak interface velocity):
   populations f <= 1e-6, g <= 1e-8, h <= 1e-7 after 2000 steps;
   u <= 1e-5 of the peak interface velocity after 2000 steps of the small
-  channel (measured 8.0e-6; the step is deterministic, so the figure
-  reproduces exactly for a given build);
+  channel, at equal densities and at density ratio 2 (measured 6.2e-7 and
+  3.9e-7; the step is deterministic, so the figures reproduce exactly for a
+  given build);
   sum phi drifts by < 1e-8 relative over 2000 steps;
   the same population bars at the full 4096 x 2048 size after 3 steps."""
 import numpy as np
@@ -137,22 +138,18 @@ def test_full_size_throughput_channel_fp32(lbm):
 
 
 def test_density_ratio_fp32(lbm):
-    """Unequal densities (rho_b = 2 below) in float32 storage, in the
-    regime the storage scheme is built for: the 128 x 64 channel heated
-    from rest, 2000 steps.  The float32 velocity error grows in proportion
-    to the density ratio (measured 8.0e-6 of the peak interface velocity at
-    equal densities, 1.6e-5 at 2), so the velocity bar, 1e-5 of the peak
-    interface velocity at equal densities, and the population bars are
-    scaled by rho_b / rho_a.  (A relaxing, strongly displaced interface
-    amplifies a one-ulp change ~700-fold, which puts float32 storage near
-    4e-5 there; the float64 parity test covers that case.)"""
+    """Unequal densities (rho_b = 2 below) in float32 storage, the 128 x 64
+    channel heated from rest, 2000 steps: the same bars as at equal
+    densities -- u within 1e-5 of the peak interface velocity (measured
+    3.9e-7; rho and u enter the g collision in float64, so 1/rho is not
+    rounded into the momentum at every step) and the population bars."""
     cfg = dict(inputs.small_channel(), rho_b=2.0)
     print("case: density ratio 2, float32, small channel 2000 steps", flush=True)
     ctx = run32(lbm, cfg, 2000)
     o = run_oracle(cfg, 2000)
-    errs = check_pops(lbm.lbm_get_state(ctx), o.pop, scale=cfg["rho_b"] / cfg["rho_a"])
+    errs = check_pops(lbm.lbm_get_state(ctx), o.pop)
     F, R = lbm.lbm_fields(ctx), o.fields()
     upk = np.nanmax(np.abs(an.interface_profile(R["ux"], R["phi"])))
     du = max(np.max(np.abs(F["ux"] - R["ux"])), np.max(np.abs(F["uy"] - R["uy"])))
     print("float32 density-ratio errors", errs, "u / peak interface u", du / upk, flush=True)
-    assert du <= 1e-5 * (cfg["rho_b"] / cfg["rho_a"]) * upk
+    assert du <= 1e-5 * upk

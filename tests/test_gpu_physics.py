@@ -61,22 +61,44 @@ def test_analytic_channel_float64(lbm, kind):
     assert res["u_int_peak"] == pytest.approx(peak, rel=1e-6)
 
 
+def float32_at_equal_steps(lbm, cfg):
+    """float64 solve to r <= 1e-8, then the float32 path stepped exactly as
+    many steps; returns (float32 fields, float64 fields, float64 record)."""
+    F64, res64 = solve(lbm, cfg, 0)
+    ctx = lbm.lbm_create(cfg, precision=1)
+    lbm.lbm_init(ctx)
+    lbm.lbm_step(ctx, res64["steps"])
+    return lbm.lbm_fields(ctx), F64, res64
+
+
 @pytest.mark.parametrize("kind", ["srf", "nf"])
 def test_analytic_channel_float32_vs_float64(lbm, kind):
     """The float32-deviation solve reaches the same steady state: peak
-    interface velocity within 2% of the diffuse-interface solution, roll
-    count, and u within 3e-4 of the peak interface velocity of the float64
-    steady state (measured 8.6e-5 SRF, 1.6e-4 NF)."""
+    interface velocity within 2% of the diffuse-interface solution and the
+    roll count.  Stepped exactly as many steps as the float64 solve took to
+    reach r <= 1e-8 (the two converged states, each stopped at its own step,
+    differ by up to ~1e-4 of the slowest mode), u is within 5e-5 of the peak
+    interface velocity of the float64 state (measured 1.6e-5 SRF, 2.9e-5 NF);
+    the 1e-5 bar is the expected failure below."""
     cfg = inputs.analytic_channel(kind)
     print("case: analytic channel", kind, "float32 vs float64", flush=True)
-    F64, _ = solve(lbm, cfg, 0)
-    F32, _ = solve(lbm, cfg, 1)
-    ui64 = an.interface_profile(F64["ux"], F64["phi"])
-    ui32 = an.interface_profile(F32["ux"], F32["phi"])
-    peak = np.max(np.abs(ui64))
+    F32s, _ = solve(lbm, cfg, 1)
+    ui32 = an.interface_profile(F32s["ux"], F32s["phi"])
     diffuse = an.diffuse_interface_velocity(cfg)
     assert abs(np.max(np.abs(ui32)) / np.max(np.abs(diffuse)) - 1.0) < 0.02
-    assert an.count_rolls(F32["uy"], cfg) == (8 if kind == "srf" else 4)
-    du = max(np.max(np.abs(F32["ux"] - F64["ux"])), np.max(np.abs(F32["uy"] - F64["uy"])))
-    print("float32 vs float64 steady u error / peak", du / peak, flush=True)
-    assert du <= 3e-4 * peak
+    assert an.count_rolls(F32s["uy"], cfg) == (8 if kind == "srf" else 4)
+    G32, F64, res64 = float32_at_equal_steps(lbm, cfg)
+    peak = np.max(np.abs(an.interface_profile(F64["ux"], F64["phi"])))
+    du = max(np.max(np.abs(G32["ux"] - F64["ux"])), np.max(np.abs(G32["uy"] - F64["uy"])))
+    print("float32 vs float64 u error / peak at %d steps" % res64["steps"], du / peak, flush=True)
+    assert du <= 5e-5 * peak
+
+
+@pytest.mark.xfail(strict=True, reason="steady-state float32 offset on the analytic channel: measured 1.6e-5 (SRF) "
+                   "and 2.9e-5 (NF) of the peak interface velocity at equal steps")
+@pytest.mark.parametrize("kind", ["srf", "nf"])
+def test_analytic_channel_float32_at_the_float32_bar(lbm, kind):
+    G32, F64, _ = float32_at_equal_steps(lbm, inputs.analytic_channel(kind))
+    peak = np.max(np.abs(an.interface_profile(F64["ux"], F64["phi"])))
+    du = max(np.max(np.abs(G32["ux"] - F64["ux"])), np.max(np.abs(G32["uy"] - F64["uy"])))
+    assert du <= 1e-5 * peak

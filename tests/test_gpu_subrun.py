@@ -9,8 +9,26 @@ so this is the case where deviation storage matters most.  Errors printed as
 a table; bounds:
   float64: populations <= 1e-11 relative max-norm, u <= 1e-11 of the
            velocity scale max|g| / (rho c_s^2);
-  float32: phi, T <= 1e-7 relative max-norm; u <= 1e-3 of the peak interface
-           velocity (measured 6.4e-4, 2.8e-11 absolute)."""
+  float32: phi, T <= 1e-7 relative max-norm; u <= 5e-4 of the peak interface
+           velocity (measured 3.4e-4, 1.5e-11 absolute).
+
+The velocity bar of the float32 path, 1e-5 of the peak interface velocity,
+is not met on this workload; that assertion is kept as a strict expected
+failure with the measured value.  The miss is a steady offset, not
+accumulated noise: started from the float64 state at step 5000 or 10000,
+the float32 run ends at the same 4e-4.  Builds that differ from the library
+only in precision bound it (the same sub-run, 20000 steps, against the
+float64 path):
+  - every operation of the step in float64, deviations still stored in
+    float32: 1.5e-5;
+  - float64 arithmetic and float64 storage of the same deviations: 1.1e-7
+    (the storage scheme itself is exact);
+  - float64 arithmetic, only the f deviations rounded to float32 when
+    stored: 1.6e-5, the g and h deviations only: 1.6e-6.
+So the float32 storage of the phase-field populations alone puts this
+channel, whose interface velocity is 4e-8 (1/200 of what the same channel
+reached during its start-up), above 1e-5; float32 arithmetic in the rest of
+the step adds the remainder."""
 import numpy as np
 import pytest
 
@@ -72,4 +90,14 @@ def test_subrun_float32(lbm, ref):
     t = table(F, R, upk)
     print("float32 sub-run errors", t, flush=True)
     assert t["phi"] <= 1e-7 and t["T"] <= 1e-7
-    assert t["u/peak"] <= 1e-3
+    assert t["u/peak"] <= 5e-4
+
+
+@pytest.mark.xfail(strict=True, reason="float32 floor on this weakly driven sub-run: u / peak interface "
+                   "velocity measured 3.4e-4 (float64 arithmetic with float32 storage: 1.5e-5); see the module "
+                   "docstring")
+def test_subrun_float32_at_the_float32_bar(lbm, ref):
+    cfg, o, R = ref
+    F, _ = run(lbm, cfg, lbm.LBM_FP32_DEV)
+    upk = np.nanmax(np.abs(an.interface_profile(R["ux"], R["phi"])))
+    assert table(F, R, upk)["u/peak"] <= 1e-5
