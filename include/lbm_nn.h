@@ -91,6 +91,20 @@ int nn_up2(int32_t backward, const uint16_t* in, uint16_t* out, int32_t n, int32
 int nn_mse(const float* pred, const float* target, uint16_t* dpred, int32_t cpad, int64_t npix, int32_t nch,
            double* loss, void* work, int64_t work_bytes, void* stream);
 
+/* nn_mse without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving or training loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results (bit for bit) as nn_mse; the per-block
+ * partial sums go to a static device array of the library (1 MiB per GPU,
+ * held until the process ends), so npix is limited to 2^25 (LBM_EINVAL
+ * beyond).  The first call on a device resolves that array's address (make
+ * it outside a stream capture).  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (two streams, two threads) race and
+ * must be ordered by the caller.  LBM_EDEVICE if the array cannot be
+ * resolved. */
+int nn_mse_noalloc(const float* pred, const float* target, uint16_t* dpred, int32_t cpad, int64_t npix, int32_t nch,
+                   double* loss, void* stream);
+
 /* One Adam step (bias-corrected, step >= 1, decoupled weight decay) on n
  * float32 parameters w with gradient g and moments m, v.  If w16 is given
  * it receives the bf16 copy; if wflip is given (convolution weights, n =

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "lbm.h"
@@ -11,6 +12,14 @@
 #include "nn_internal.h"
 
 using namespace nn;
+
+// Scratch of the allocation-free loss (nn_mse_noalloc): one float64 partial
+// sum per 256 pixels.  Each GPU the library runs on holds its own copy until
+// the process ends.  In host code the name below is only a stand-in for the
+// device array; kernels get the address resolved per device by
+// hipGetSymbolAddress (scratch_on_current_device).
+constexpr long long MSE_SCRATCH_DOUBLES = 131072;                 // 1 MiB: up to 2^25 pixels
+static __device__ __align__(256) double scratch[MSE_SCRATCH_DOUBLES];
 
 namespace {
 
@@ -29,6 +38,25 @@ long long wgrad_chunk_pix(long long npix) {
     long long c = (npix + 255) / 256;
     c = ((c + 63) / 64) * 64;
     return c < 64 ? 64 : c;
+}
+
+// Device address of `scratch` on the current device, resolved once per
+// device with that device current (each GPU has its own copy).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+int scratch_on_current_device(double** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return LBM_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EDEVICE;
+        g_scratch[dev] = (double*)ptr;
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
 }
 
 ChanDesc desc_of(const lbm_params& p) {
@@ -160,6 +188,18 @@ int nn_mse(const float* pred, const float* target, uint16_t* dpred, int32_t cpad
     if (!pred || !target || !loss || !work || npix <= 0 || nch <= 0 || (dpred && cpad < nch)) return LBM_EINVAL;
     if (work_bytes < 8 * ((npix + 255) / 256)) return LBM_EINVAL;
     return status(launch_mse(pred, target, dpred, (double*)work, loss, npix, nch, dpred ? cpad : 0, S(stream)));
+}
+
+int nn_mse_noalloc(const float* pred, const float* target, uint16_t* dpred, int32_t cpad, int64_t npix, int32_t nch,
+                   double* loss, void* stream) {
+    if (!pred || !target || !loss || npix <= 0 || nch <= 0 || (dpred && cpad < nch)) return LBM_EINVAL;
+    if ((npix + 255) / 256 > MSE_SCRATCH_DOUBLES) return LBM_EINVAL;   // beyond the static scratch
+    double* work = nullptr;
+    const int rc = scratch_on_current_device(&work);
+    if (rc) return rc;
+    // every partial slot the launch reads is written first by the same launch:
+    // nothing to clear
+    return status(launch_mse(pred, target, dpred, work, loss, npix, nch, dpred ? cpad : 0, S(stream)));
 }
 
 int nn_adam(float* w, uint16_t* w16, uint16_t* wflip, const float* g, float* m, float* v, int64_t n, int32_t co,

@@ -12,7 +12,7 @@ import ctypes
 from . import lbm as _lbm
 
 EXPORTS = ("nn_conv3x3_fwd", "nn_conv3x3_bwd_data", "nn_conv3x3_wgrad_workspace", "nn_conv3x3_bwd_weight",
-           "nn_relu_bwd", "nn_add", "nn_pool2", "nn_up2", "nn_mse", "nn_adam", "nn_cast_weights", "nn_features",
+           "nn_relu_bwd", "nn_add", "nn_pool2", "nn_up2", "nn_mse", "nn_mse_noalloc", "nn_adam", "nn_cast_weights", "nn_features",
            "nn_to_fields", "nn_targets", "nn_velocity_scale")
 
 _loaded = None
@@ -34,6 +34,7 @@ def load():
     L.nn_pool2.argtypes = [i32, vp, vp, i32, i32, i32, i32, vp]
     L.nn_up2.argtypes = [i32, vp, vp, i32, i32, i32, i32, vp]
     L.nn_mse.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, i64, vp]
+    L.nn_mse_noalloc.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp]
     L.nn_adam.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, i32, i64, f32, f32, f32, f32, f32, vp]
     L.nn_cast_weights.argtypes = [vp, vp, vp, i32, i32, vp]
     L.nn_features.argtypes = [pp, i32, vp, i32, vp]
@@ -110,6 +111,11 @@ def nn_mse(pred, target, dpred, cpad, npix, nch, loss, work):
     nbytes = work.numel() * work.element_size()
     _check(load().nn_mse(_p(pred), _p(target), _p(dpred), int(cpad), int(npix), int(nch), _p(loss), _p(work),
                          nbytes, _stream()), "nn_mse")
+
+
+def nn_mse_noalloc(pred, target, dpred, cpad, npix, nch, loss):
+    _check(load().nn_mse_noalloc(_p(pred), _p(target), _p(dpred), int(cpad), int(npix), int(nch), _p(loss),
+                                 _stream()), "nn_mse_noalloc")
 
 
 def nn_adam(w, w16, wflip, g, m, v, co, ci, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
