@@ -46,6 +46,16 @@ struct lbm_ctx {
     void* phir = nullptr;              // zeroth moment of the streamed reference populations minus phi0, by row
     void* fq = nullptr;                // flux reference of f (half its y-moment) by row
     void* fr = nullptr;                // constant part of the stored post-collision y-moment of f by row
+    // float32 mode: the flux reference follows the actual flux (moved after
+    // every check); the set-up tables are kept to start from again
+    float* fq_next = nullptr;
+    float* fr_next = nullptr;
+    float* fr_sw = nullptr;
+    float* fq_cold = nullptr;
+    float* fr_cold = nullptr;
+    double* frc = nullptr;             // (1 - w_phi) r01 + w_phi M theta0 n0y by row
+    double* rowpart = nullptr;         // check-step row sums of the flux deviation [rows][ceil(nx/16)]
+    int max_rows = 0;
     double* twall = nullptr;           // bottom-wall temperature by column (float64 in both precisions)
     float* tref = nullptr;             // per-node temperature reference (float32 mode)
     float* tref_new = nullptr;         // references written by a check step
@@ -223,6 +233,8 @@ void step_args(lbm_ctx* c, StepArgs& a, bool parity) {
     a.phir_v = c->phir;
     a.fq_v = c->fq;
     a.fr_v = c->fr;
+    a.fqw_v = c->fq;
+    a.rowpart = c->rowpart;
     a.tref_v = c->tref;
     a.tref_out = c->tref_new;
     a.dl_v = c->dl;
@@ -242,14 +254,50 @@ void fin_args(lbm_ctx* c, FinArgs& f) {
     f.tol = c->d_tol;
 }
 
+void flux_args(lbm_ctx* c, FluxArgs& f) {
+    f.insts = c->d_inst;
+    f.fq = (float*)c->fq;
+    f.fq_next = c->fq_next;
+    f.fr = (float*)c->fr;
+    f.fr_next = c->fr_next;
+    f.fr_sw = c->fr_sw;
+    f.frc = c->frc;
+    f.rowpart = c->rowpart;
+}
+
+// Float32 mode: every flux table of rows [r0, r0 + n) back to the set-up one.
+int reset_flux_tables(lbm_ctx* c, long long r0, long long n) {
+    if (c->prec != LBM_FP32_DEV || n <= 0) return LBM_OK;
+    const size_t b = (size_t)n * sizeof(float);
+    float* dst[5] = {(float*)c->fq + r0, c->fq_next + r0, (float*)c->fr + r0, c->fr_next + r0, c->fr_sw + r0};
+    const float* src[5] = {c->fq_cold + r0, c->fq_cold + r0, c->fr_cold + r0, c->fr_cold + r0, c->fr_cold + r0};
+    for (int k = 0; k < 5; ++k)
+        HIPCHK(c, hipMemcpyAsync(dst[k], src[k], b, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
 // One step starting at global step index `s` (state in buffer s % 2).
 int enqueue_step(lbm_ctx* c, long long s) {
     StepArgs a;
     step_args(c, a, (s & 1) != 0);
     const bool check = (s % CHECK_EVERY) == 0;
+    // float32 mode: the step after a check stores its f populations against
+    // the flux reference that check computed
+    const bool flux_switch = c->prec == LBM_FP32_DEV && (s % CHECK_EVERY) == 1;
+    if (flux_switch) {
+        a.fqw_v = c->fq_next;
+        a.fr_v = c->fr_sw;
+    }
     if (c->n_tiles > 0) {
         hipError_t e = launch_step(c->prec, a, check ? 1 : 0, grid_of(c->n_tiles), c->tx, c->ty, c->stream);
         if (e != hipSuccess) return fail_hip(c, e, "step kernel launch");
+    }
+    if ((check || flux_switch) && c->prec == LBM_FP32_DEV) {
+        FluxArgs fa;
+        flux_args(c, fa);
+        hipError_t e = check ? launch_flux_next(fa, c->n_inst, c->stream)
+                             : launch_flux_copy(fa, c->max_rows, c->n_inst, c->stream);
+        if (e != hipSuccess) return fail_hip(c, e, "flux reference launch");
     }
     if (check && c->prec == LBM_FP32_DEV) {
         // the check step stored its populations relative to new temperature
@@ -362,7 +410,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     c->stream = (hipStream_t)hip_stream;
     // layout
     c->h_inst.resize(n_inst);
-    long long pop = 0, nodes = 0, rows = 0, cols = 0, chunks = 0;
+    long long pop = 0, nodes = 0, rows = 0, cols = 0, chunks = 0, rp = 0;
     long long max_tiles = 0;
     for (int k = 0; k < n_inst; ++k) {
         const lbm_params& p = params[k];
@@ -376,6 +424,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         I.row_off = rows;
         I.col_off = cols;
         I.chunk_off = chunks;
+        I.rp_off = rp;
+        I.rp_stride = (p.nx + 15) / 16;
         I.W = p.W;
         I.M_phi = p.M_phi;
         I.w_phi = 1.0 / (3.0 * p.M_phi + 0.5);
@@ -395,6 +445,8 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         nodes += n;
         rows += p.ny + 4;
         cols += p.nx;
+        rp += (long long)p.ny * ((p.nx + 15) / 16);
+        c->max_rows = std::max(c->max_rows, p.ny);
         {
             const long long ch = (long long)((p.nx + DLZ_CX - 1) / DLZ_CX) * ((p.ny + DLZ_CY - 1) / DLZ_CY);
             chunks += ch;
@@ -426,7 +478,16 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         c->dl = (int32_t*)dev_alloc(c, (size_t)nodes * sizeof(int32_t));
         c->dl_new = (int32_t*)dev_alloc(c, (size_t)nodes * sizeof(int32_t));
         c->dlz = (int32_t*)dev_alloc(c, (size_t)chunks * sizeof(int32_t));
-        if (!c->tref || !c->tref_new || !c->dl || !c->dl_new || !c->dlz) rc = LBM_ENOMEM;
+        c->fq_next = (float*)dev_alloc(c, (size_t)rows * sizeof(float));
+        c->fr_next = (float*)dev_alloc(c, (size_t)rows * sizeof(float));
+        c->fr_sw = (float*)dev_alloc(c, (size_t)rows * sizeof(float));
+        c->fq_cold = (float*)dev_alloc(c, (size_t)rows * sizeof(float));
+        c->fr_cold = (float*)dev_alloc(c, (size_t)rows * sizeof(float));
+        c->frc = (double*)dev_alloc(c, (size_t)rows * sizeof(double));
+        c->rowpart = (double*)dev_alloc(c, (size_t)rp * sizeof(double));
+        if (!c->tref || !c->tref_new || !c->dl || !c->dl_new || !c->dlz || !c->fq_next || !c->fr_next || !c->fr_sw ||
+            !c->fq_cold || !c->fr_cold || !c->frc || !c->rowpart)
+            rc = LBM_ENOMEM;
     }
     c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
     c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
@@ -470,7 +531,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         // them, so the kernel relaxes only deviations (tiny near steady
         // state).  Any A is exact up to rounding; this one makes the stored
         // values small.
-        std::vector<double> t0(rows, 0.0), tr(rows, 0.0), tq(rows, 0.0), tf(rows, 0.0);
+        std::vector<double> t0(rows, 0.0), tr(rows, 0.0), tq(rows, 0.0), tf(rows, 0.0), tc(rows, 0.0);
         if (precision == LBM_FP32_DEV) {
             const int EYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
             const double Wh[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
@@ -557,6 +618,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
                     const double fq_sum = qq[j - 1] + qq[j + 1];
                     const double rest = mth(q0[j], 0.5 * (q0[j + 1] - q0[j - 1]));
                     qf[j] = (double)(float)((1.0 - w) * (r01[j] + fq_sum) + w * rest - 2.0 * qq[j]);
+                    tc[c->h_inst[k].row_off + 2 + j] = (1.0 - w) * r01[j] + w * rest;
                 }
             }
         }
@@ -578,6 +640,17 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         if (upload(c->phi0, t0) != hipSuccess || upload(c->phir, tr) != hipSuccess || upload(c->fq, tq) != hipSuccess ||
             upload(c->fr, tf) != hipSuccess)
             rc = fail_hip(c, hipErrorUnknown, "upload reference rows");
+        if (rc == LBM_OK && precision == LBM_FP32_DEV) {
+            // the set-up flux tables, kept to start from again (lbm_init, lbm_restart)
+            std::vector<float> q32(tq.begin(), tq.end()), f32(tf.begin(), tf.end());
+            hipError_t e = hipMemcpyAsync(c->fq_cold, q32.data(), rows * sizeof(float), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->fr_cold, f32.data(), rows * sizeof(float), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->frc, tc.data(), rows * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rc = fail_hip(c, e, "upload flux tables");
+        }
     }
     if (rc == LBM_OK) {
         // bottom-wall temperature T_h + dT cos(2 pi i / l) for every column
@@ -652,6 +725,8 @@ static int init_impl(lbm_ctx* c, const double* fields, bool device) {
     HIPCHK(c, hipMemsetAsync(c->d_res, 0, sizeof(Result) * c->n_inst, c->stream));
     HIPCHK(c, hipMemsetAsync(c->d_counter, 0, sizeof(long long), c->stream));
     HIPCHK(c, hipMemsetAsync(c->snap, 0, sizeof(double) * 4 * c->total_nodes, c->stream));
+    rc = reset_flux_tables(c, 0, c->total_rows);
+    if (rc) return rc;
     InitArgs a;
     a.insts = c->d_inst;
     a.dst_v = c->popA;
@@ -825,6 +900,8 @@ int lbm_restart(lbm_ctx* c, int32_t inst, const double* fields) {
         HIPCHK(c, hipMemcpyAsync(dfields, fields, sizeof(double) * 4 * n, hipMemcpyHostToDevice, c->stream));
         for (int f = 0; f < 4; ++f) a.fields[f] = dfields + f * n;
     }
+    rc = reset_flux_tables(c, I.row_off, (long long)c->params[inst].ny + 4);
+    if (rc) return rc;
     const Result zero{};
     const int one = 1;
     HIPCHK(c, hipMemcpyAsync(c->d_res + inst, &zero, sizeof(Result), hipMemcpyHostToDevice, c->stream));

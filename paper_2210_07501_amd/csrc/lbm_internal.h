@@ -38,6 +38,8 @@ struct Inst {
     long long row_off;            // offset in the reference-row table (ny + 4 rows)
     long long col_off;            // offset in the bottom-wall temperature table (nx columns)
     long long chunk_off;          // offset in the phi-offset flag table (ceil(nx/64) x ceil(ny/8) chunks)
+    long long rp_off;             // offset in the row-partial table of the flux reference (ny x rp_stride)
+    int rp_stride, pad3;          // rp_stride = ceil(nx / 16): tile columns of the narrowest tile shape
     double W, M_phi, w_phi, b;
     double rho_a, rho_b, mu_a, mu_b, k_a, k_b;
     double s0, sT, sTT, T_ref;
@@ -63,6 +65,9 @@ struct StepArgs {
     const void* phir_v;           // zeroth moment of the streamed reference populations minus phi0, by row
     const void* fq_v;             // flux reference: half the reference y-moment of f, by row
     const void* fr_v;             // constant part of the stored post-collision y-moment of f, by row
+    const void* fqw_v;            // flux reference the writer subtracts (float32 mode): fq_v, except on
+                                  // the step after a check, which moves to the new table
+    double* rowpart;              // check steps: per row and tile column, sum of the f flux deviations
     const void* tref_v;           // per-node temperature reference (float32 mode)
     void* tref_out;               // new references written by a check step
     const int32_t* dl_v;          // per-node phi-reference offset from phi0(row), in units of DL_Q (float32 mode)
@@ -108,6 +113,20 @@ struct StateArgs {
     double* state;                // device [3][9][ny][nx] float64
 };
 
+// Flux reference of f (float32 mode), moved after every check to the row
+// mean of the actual flux (see flux_next_kernel).  Tables by row (ny + 4 per
+// channel, float values): fq = A/2 read by the pulls, fr its companion.
+struct FluxArgs {
+    const Inst* insts;
+    float* fq;                    // current
+    float* fq_next;               // after the next switch step
+    float* fr;                    // current
+    float* fr_next;               // after the switch step
+    float* fr_sw;                 // for the switch step itself (reads fq, writes fq_next)
+    const double* frc;            // (1 - w_phi) r01 + w_phi M theta0 n0y by row (float64)
+    const double* rowpart;
+};
+
 struct TrefArgs {
     const Inst* insts;
     float* tref;
@@ -123,6 +142,8 @@ hipError_t launch_count_active(const Inst* insts, int n, int* out, hipStream_t s
 hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, hipStream_t st);
 hipError_t launch_state(int prec, const StateArgs& a, int nodes, hipStream_t st);
 hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStream_t st);
+hipError_t launch_flux_next(const FluxArgs& a, int n_inst, hipStream_t st);
+hipError_t launch_flux_copy(const FluxArgs& a, int max_rows, int n_inst, hipStream_t st);
 hipError_t launch_dl_flags(const Inst* insts, const int32_t* dl, int32_t* dlz, int max_chunks, int n_inst,
                            hipStream_t st);
 

@@ -426,13 +426,19 @@ void step_kernel(StepArgs a) {
     const bool own_row = gj < ny;
     const bool own_ok = own_row && (x0 + tx < nx);
     R f[9], g[9], h[9];
-    R rf[9], rg[9], rh[9];
+    R rf[9], rh[9];
+    double rg[9];   // moments of g in float64: they feed the float64 g collision
     const R Tro = DEV ? s_Tr[(ty + 2) * LX2 + tx + 2] : R(0);   // this node's T reference
     double dph_d = 0.0;   // float32 mode: phi - phi0(row), accumulated in float64
     if (own_row) {
         pull_node<S, R, 7>(src, tw, p, gi, gj, Tro, f, g, h);
         raw_moments(f, rf);
-        raw_moments(g, rg);
+        {
+            double gd[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) gd[q] = (double)g[q];
+            raw_moments(gd, rg);
+        }
         raw_moments(h, rh);
         if (DEV) {
             R c0, cx, cy;
@@ -581,6 +587,7 @@ void step_kernel(StepArgs a) {
 
     // ---- phase 3: forces, velocity, collisions -------------------------------
     double red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double flux_dev = 0.0;   // float32 check steps: this node's stored f flux deviation t01 - A
     if (own_row) {
         const R cs2 = R(1) / R(3);
         const int c2 = (ty + 2) * LX2 + tx + 2, c1 = (ty + 1) * LX1 + tx + 1;
@@ -738,6 +745,7 @@ void step_kernel(StepArgs a) {
                     const R dth = R(4) * dph * (R(1) - phi - ph0) * p.inv_W;   // theta - theta0
                     const R dtn = dth * nyv + th0 * s_dny[c1];                  // theta n_y - theta0 n0y
                     t01 = dk01 + p.w_phi * (p.M * dtn - dk01) + s_fr[ty + 2];
+                    if (MODE == 1 && own_ok) flux_dev = (double)t01;
                 } else {
                     const R k01 = rf[1] - uy * phi;
                     t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
@@ -755,8 +763,9 @@ void step_kernel(StepArgs a) {
                 c[7] = phr * uy * (cs2 + ux2);               // 21
                 c[8] = dphr * (cs2 * cs2) - phr * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
                 if (DEV) {
-                    // minus the other central moments of q (raw: m01 = A only)
-                    const R A = R(2) * s_fq[ty + 3];
+                    // minus the other central moments of q (raw: m01 = A only),
+                    // the flux reference this step stores against
+                    const R A = R(2) * ((const R*)a.fqw_v)[I.row_off + gj + 2];
                     c[2] += R(2) * A * uy;
                     c[4] += A * ux;
                     c[5] -= R(2) * A * uxy;
@@ -847,6 +856,25 @@ void step_kernel(StepArgs a) {
                     store_pop((S*)((char*)dst.plane(2, q) + bo), S(h[q]));
                 }
             }
+        }
+    }
+    if (MODE == 1 && DEV) {
+        // row sums of the stored flux deviation over this tile, in a fixed
+        // order (segments of TX lanes, then the segments of a row), for the
+        // flux reference that follows the actual flux
+        constexpr int SEG = TX < 64 ? TX : 64;
+        constexpr int NSEG = TX / SEG;
+        __shared__ double s_rs[TY * NSEG];
+        double v = flux_dev;
+#pragma unroll
+        for (int o = SEG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (tid % SEG == 0) s_rs[tid / SEG] = v;
+        __syncthreads();
+        if (tid < TY && y0 + tid < ny) {
+            double r = 0.0;
+#pragma unroll
+            for (int k = 0; k < NSEG; ++k) r += s_rs[tid * NSEG + k];
+            a.rowpart[I.rp_off + (size_t)(y0 + tid) * I.rp_stride + tcol] = r;
         }
     }
     if (MODE == 1) {
@@ -1126,6 +1154,55 @@ __global__ __launch_bounds__(256) void tref_copy_kernel(TrefArgs a) {
     a.dl[I.node_off + q] = a.dl_new[I.node_off + q];
 }
 
+// Float32 mode, after a check step: the flux reference A = 2 fq of f moves
+// to the row mean of the actual post-collision flux (the check step's row
+// sums of the stored deviation t01 - A, over the channel's tile columns in a
+// fixed order).  Near a steady, nearly flat interface the stored flux
+// deviations then shrink to their variation along x.  Also forms fr for the
+// new table (fr_next) and for the switch step that reads the old table and
+// writes against the new one (fr_sw):
+//   fr = (1 - w) (r01 + fq_read(j-1) + fq_read(j+1)) + w M theta0 n0y - 2 fq_write(j).
+// One block per channel; channels retired before this check are left alone.
+__global__ __launch_bounds__(256) void flux_next_kernel(FluxArgs a) {
+    const Inst& I = a.insts[blockIdx.x];
+    if (!I.active) return;
+    const int ny = I.ny;
+    const long long r0 = I.row_off + 2;            // row j lives at r0 + j
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < I.tiles_x; ++c) s += a.rowpart[I.rp_off + (size_t)j * I.rp_stride + c];
+        a.fq_next[r0 + j] = (float)((double)a.fq[r0 + j] + 0.5 * s / (double)I.nx);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {                        // wall images, as the set-up builds them
+        a.fq_next[r0 - 1] = -a.fq_next[r0];
+        a.fq_next[r0 + ny] = -a.fq_next[r0 + ny - 1];
+        a.fq_next[r0 - 2] = a.fq[r0 - 2];
+        a.fq_next[r0 + ny + 1] = a.fq[r0 + ny + 1];
+    }
+    __syncthreads();
+    const double wl = 1.0 - I.w_phi;
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+        const double c = a.frc[r0 + j], qn = 2.0 * (double)a.fq_next[r0 + j];
+        a.fr_next[r0 + j] = (float)(c + wl * ((double)a.fq_next[r0 + j - 1] + (double)a.fq_next[r0 + j + 1]) - qn);
+        a.fr_sw[r0 + j] = (float)(c + wl * ((double)a.fq[r0 + j - 1] + (double)a.fq[r0 + j + 1]) - qn);
+    }
+}
+
+// After the switch step: the new flux tables become current (channels that
+// took part in that step only); a later switch without a new check is then
+// the identity.
+__global__ __launch_bounds__(256) void flux_copy_kernel(FluxArgs a) {
+    const Inst& I = a.insts[blockIdx.y];
+    if (!I.active) return;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= I.ny + 4) return;
+    const long long r = I.row_off + k;
+    a.fq[r] = a.fq_next[r];
+    a.fr[r] = a.fr_next[r];
+    a.fr_sw[r] = a.fr_next[r];
+}
+
 // Chunk flags of the phi-reference offsets: one wave per 64 x 8 chunk, one
 // lane per column; the flag is 1 when any offset in the chunk is nonzero.
 __global__ __launch_bounds__(DLZ_CX) void dl_flags_kernel(const Inst* insts, const int32_t* dl, int32_t* dlz) {
@@ -1198,6 +1275,16 @@ hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, h
 
 hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStream_t st) {
     hipLaunchKernelGGL(tref_copy_kernel, dim3((max_nodes + 255) / 256, n_inst), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_next(const FluxArgs& a, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(flux_next_kernel, dim3(n_inst), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_copy(const FluxArgs& a, int max_rows, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(flux_copy_kernel, dim3((max_rows + 4 + 255) / 256, n_inst), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
