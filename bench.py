@@ -7,14 +7,19 @@ bottom layer 0.3 of the height, viscosity ratio 0.5, conductivity ratio 2,
 sigma_T = -5e-5, sigma_TT = 2e-4, cold start.  A step is one pass of the
 whole hot path: the fused collide-stream kernel over the lattice, plus (every
 100th step) the float64 residual / conserved-sum reduction and its check
-kernel.  Inputs are resident in HBM before timing starts.
+kernels.  Inputs are resident in HBM before timing starts.  Warm-up: the
+given --warmup steps, at least 20 and rounded up to a multiple of 100, so
+that the timed window starts with a check step.
 
 Prints one JSON line: MLUPS of the float64 path (value), the float32-deviation
 path alongside, the roofline of the dominant kernel (HBM-bound; algorithmic
-bytes 432 B per node update in float64, 216 B in float32), the time to
-steady state of 16 held-out 256 x 128 channels (plain float64 channel by
-channel vs one warm-started float32 batch vs one cold float32 batch), and
-the CPU oracle's rate on a bounded sample.
+bytes 432 B per node update in float64, 216 B in float32), the error of both
+paths against the float64 oracle on the 256 x 128 sub-run of the same
+channel (20000 steps), the 256-channel batched sweep (seed 2210, float32,
+autotuned tile) timed over a fixed window of launches, the time to steady
+state of 16 of the 256 held-out 256 x 128 warm-start channels (plain
+float64 channel by channel vs one warm-started float32 batch vs one cold
+float32 batch), and the CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -34,11 +39,17 @@ BYTES_PER_UPDATE = {0: 27 * 2 * 8, 1: 27 * 2 * 4}
 # 1.0 of the every-step kernel, the factors read off a 1 GiB device copy),
 # tile 64x8; profiles/step_kernel_4096x2048_hbm_bytes.md.  Set to None when
 # the step kernel changes until it is measured again.
-MEASURED_TRAFFIC = {0: 497.1, 1: 235.9}
+MEASURED_TRAFFIC = {0: 496.3, 1: 236.0}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def warmup_steps(w: int) -> int:
+    """Untimed steps before the timed window: at least w and 20, rounded up to
+    a multiple of the check interval (100) so the window starts with a check."""
+    return -(-max(int(w), 20) // 100) * 100
 
 
 def run_gpu(cfg, prec, steps, warmup, tile):
@@ -51,7 +62,7 @@ def run_gpu(cfg, prec, steps, warmup, tile):
         lbm.lbm_set_tile(ctx, *tile)
     lbm.lbm_init(ctx)
     nodes, _ = lbm.lbm_info(ctx)
-    lbm.lbm_step(ctx, warmup)
+    lbm.lbm_step(ctx, warmup_steps(warmup))
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -98,34 +109,40 @@ def copy_ceiling(nbytes=1 << 30, reps=20):
     return best
 
 
-def cpu_baseline(target_s=12.0, target_1=6.0):
+def cpu_baseline(subrun_steps=20_000, target_1=6.0):
     """The FP64 oracle, as it stands, on the 256 x 128 sub-run of the same
     channel geometry (scaled by 1/16), timed on this host's cores: all
-    threads (the reported value) and one thread."""
+    threads on the whole sub-run (20000 steps from rest, the reported value)
+    and one thread on a shorter sample.  Also returns the oracle's fields at
+    the end of the sub-run and its peak interface velocity, which the
+    sub-run error table of the GPU paths is measured against."""
+    import numpy as np
+
+    from oracle import analytic as an
     from oracle import oracle as orc
     from paper_2210_07501_amd import inputs
 
     cfg = inputs.throughput_channel(scale=16)
     nodes = cfg["nx"] * cfg["ny"]
-
-    def rate(target):
-        o = orc.Oracle(cfg)
-        o.init_cold()
-        o.step(10)                                   # thread start-up, caches
-        t = time.perf_counter()
-        o.step(10)
-        chunk = max(10, int(1.0 / max((time.perf_counter() - t) / 10, 1e-6)))   # about 1 s
-        n, t = 0, time.perf_counter()
-        while time.perf_counter() - t < target:      # timed in chunks until the target is reached
-            o.step(chunk)
-            n += chunk
-        dt = time.perf_counter() - t
-        return nodes * n / dt / 1e6, n, dt
-
     threads = orc.max_threads()
-    v, n, dt = rate(target_s)
+    o = orc.Oracle(cfg)
+    o.init_cold()
+    t = time.perf_counter()
+    o.step(subrun_steps)
+    dt = time.perf_counter() - t
+    R = o.fields()
+    upk = float(np.nanmax(np.abs(an.interface_profile(R["ux"], R["phi"]))))
+
     orc.set_threads(1)
-    v1, n1, dt1 = rate(target_1)
+    o1 = orc.Oracle(cfg)
+    o1.init_cold()
+    o1.step(10)
+    t1 = time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t1 < target_1:
+        o1.step(20)
+        n1 += 20
+    dt1 = time.perf_counter() - t1
     orc.set_threads(threads)
     model = ""
     try:
@@ -135,9 +152,72 @@ def cpu_baseline(target_s=12.0, target_1=6.0):
                 break
     except OSError:
         pass
-    return dict(value=v, unit="MLUPS", cores=threads, kind="oracle",
-                sample="256x128 sub-run of the throughput channel (1/16 scale), %d steps from rest, %.1f s" % (n, dt),
-                single_thread_value=v1, single_thread_sample="%d steps, %.1f s" % (n1, dt1), cpu_model=model)
+    base = dict(value=nodes * subrun_steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample="256x128 sub-run of the throughput channel (1/16 scale), %d steps from rest, %.1f s"
+                       % (subrun_steps, dt),
+                single_thread_value=nodes * n1 / dt1 / 1e6, single_thread_sample="%d steps, %.1f s" % (n1, dt1),
+                cpu_model=model)
+    return base, R, upk
+
+
+def subrun_errors(R, upk, steps=20_000):
+    """Error of both GPU paths on the 256 x 128 sub-run of the throughput
+    channel (geometry scaled by 1/16), 20000 steps from rest, against the
+    oracle's fields R of the same run (cpu_baseline): relative max-norm of
+    phi, T, p, and the largest velocity error over the oracle's peak
+    interface velocity upk."""
+    import numpy as np
+
+    from paper_2210_07501_amd import inputs, lbm
+
+    cfg = inputs.throughput_channel(scale=16)
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    out = {"workload": "256x128 sub-run of the throughput channel, %d steps from rest" % steps,
+           "peak_interface_u": upk}
+    for prec, name in ((lbm.LBM_FP64, "fp64"), (lbm.LBM_FP32_DEV, "fp32_dev")):
+        ctx = lbm.lbm_create(cfg, precision=prec)
+        lbm.lbm_init(ctx)
+        lbm.lbm_step(ctx, steps)
+        F = lbm.lbm_fields(ctx)
+        lbm.lbm_destroy(ctx)
+        du = max(float(np.max(np.abs(F["ux"] - R["ux"]))), float(np.max(np.abs(F["uy"] - R["uy"]))))
+        out[name] = {"phi": rel(F["phi"], R["phi"]), "T": rel(F["T"], R["T"]), "p": rel(F["p"], R["p"]),
+                     "u_abs": du, "u_over_peak_interface_u": du / upk}
+    return out
+
+
+def batched_sweep_leg(steps=300, warmup=100):
+    """The 256-channel batched sweep (seed 2210: nx in {128, 256, 512},
+    ny = nx / 2, 14.6 M nodes) in float32, tile chosen by lbm_autotune, cold
+    start, timed over a fixed window of `steps` launches (it contains three
+    check steps); MLUPS and the fraction of the HBM roofline at 216 B per
+    node update."""
+    import torch
+
+    from paper_2210_07501_amd import inputs, lbm
+
+    cfgs = inputs.batched_sweep(256, 2210)
+    ctx = lbm.lbm_create(cfgs, precision=lbm.LBM_FP32_DEV)
+    lbm.lbm_init(ctx)
+    (tx, ty), tune_ms = lbm.lbm_autotune(ctx, 10)
+    nodes, dev_bytes = lbm.lbm_info(ctx)
+    lbm.lbm_step(ctx, warmup)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    lbm.lbm_step(ctx, steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    lbm.lbm_destroy(ctx)
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    gbs = mlups * 1e6 * BYTES_PER_UPDATE[1] / 1e9
+    return {"workload": "batched sweep, 256 channels (seed 2210), float32-deviation storage, cold start",
+            "nodes": nodes, "channels": len(cfgs), "tile": "%dx%d" % (tx, ty), "device_bytes": dev_bytes,
+            "steps": steps, "warmup": warmup, "ms_per_step": round(ms / steps, 4), "value": round(mlups, 1),
+            "unit": "MLUPS", "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def time_to_steady(n=16, cap=400_000):
@@ -177,7 +257,8 @@ def time_to_steady(n=16, cap=400_000):
     log("bench: warm batch %.1f s, cold batch %.1f s" % (wall_w + t_nn, wall_c))
     conv = lambda res: int(sum(r["r"] <= 1e-8 for r in res))
     med = lambda res: int(np.median([r["steps"] for r in res]))
-    return {"channels": n, "workload": "held-out warm-start channels 256x128 (seeds 900000+i)",
+    return {"channels": n, "subset_of": 256,
+            "workload": "the first %d of the 256 held-out warm-start channels 256x128 (seeds 900000+i)" % n,
             "cold_fp64_single_s": round(t_single, 2), 
             "warm_fp32_batch_s": round(wall_w + t_nn, 2), "inference_s": round(t_nn, 3),
             "cold_fp32_batch_s": round(wall_c, 2),
@@ -196,6 +277,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true",
                     help="skip the time-to-steady comparison (16 held-out channels, about a minute)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 256-channel batched sweep window")
     ap.add_argument("--tile", type=str, default="")
     ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both")
     ap.add_argument("--calib-copy", action="store_true",
@@ -228,8 +310,8 @@ def main():
              "fp32": (lbm.LBM_FP32_DEV,)}[args.precision]
     out = {}
     for prec in precs:
-        log("bench: precision %d, %d warmup + %d timed steps on %dx%d" % (prec, args.warmup, args.steps,
-                                                                        cfg["nx"], cfg["ny"]))
+        log("bench: precision %d, %d warmup + %d timed steps on %dx%d" % (prec, warmup_steps(args.warmup),
+                                                                        args.steps, cfg["nx"], cfg["ny"]))
         out[prec] = run_gpu(cfg, prec, args.steps, args.warmup, tile)
         log("bench: done", out[prec]["ms_total"], "ms")
 
@@ -268,7 +350,8 @@ def main():
     mlups32 = r32["nodes"] * args.steps / (r32["ms_total"] * 1e-3) / 1e6
     line = {
         "metric": METRIC, "value": round(mlups64, 1), "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r64["ms_total"] / args.steps, 4),
+        "steps": args.steps, "warmup": args.warmup, "warmup_launches": warmup_steps(args.warmup),
+        "ms_per_step": round(r64["ms_total"] / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "throughput channel 4096x2048, 8 heating wavelengths, lower layer 0.3, "
@@ -278,12 +361,19 @@ def main():
         "fp32_dev": {"value": round(mlups32, 1), "unit": "MLUPS", "dtype": "f32",
                      "ms_per_step": round(r32["ms_total"] / args.steps, 4), "roofline": roof(lbm.LBM_FP32_DEV)},
     }
+    if not args.no_sweep:
+        log("bench: batched sweep, 256 channels")
+        line["c3_sweep"] = batched_sweep_leg()
     if not args.no_warmstart:
         log("bench: time to steady state (warm-started batch vs cold float64 channel by channel)")
         line["time_to_steady"] = time_to_steady()
     if not args.no_cpu:
-        log("bench: CPU oracle baseline")
-        line["cpu_baseline"] = cpu_baseline()
+        # the oracle's own run of the sub-run is both the CPU baseline and the
+        # reference of the sub-run error table
+        log("bench: CPU oracle baseline (256x128 sub-run, 20000 steps)")
+        line["cpu_baseline"], R, upk = cpu_baseline()
+        log("bench: sub-run errors against the float64 oracle")
+        line["c2_subrun_error"] = subrun_errors(R, upk)
     print(json.dumps(line), flush=True)
 
 
