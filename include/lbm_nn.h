@@ -46,6 +46,14 @@ int nn_conv3x3_fwd(const uint16_t* x, const uint16_t* w, const float* bias, uint
                    int32_t y32_channels, int32_t n, int32_t h, int32_t wd, int32_t ci, int32_t co, int32_t relu,
                    void* stream);
 
+/* Tuning: the row-walking forward kernel (rows of 256 or 128 pixels, the
+ * channel pairs of the network's two upper levels) lets one work-group walk
+ * down several consecutive row steps of an image, sharing input rows.
+ * steps > 0 fixes how many (used when it divides the steps of an image, else
+ * 1); 0 restores the automatic choice.  Library-wide setting; results do not
+ * depend on it.  LBM_EINVAL for steps < 0 or > 64. */
+int nn_set_conv_walk(int32_t steps);
+
 /* dx = gradient of the convolution with respect to its input: dy
  * [n][h][wd][co] bf16, wflip [ci][9][co] bf16, dx [n][h][wd][ci] bf16. */
 int nn_conv3x3_bwd_data(const uint16_t* dy, const uint16_t* wflip, uint16_t* dx, int32_t n, int32_t h, int32_t wd,

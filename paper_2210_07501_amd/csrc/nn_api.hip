@@ -32,12 +32,13 @@ bool conv_shape_ok(int n, int h, int w, int ci, int co) {
            co % 32 == 0 && co <= MAX_CH;
 }
 
-// pixel chunks of the weight gradient: multiples of 64 pixels, about 256
-// chunks, a function of the sizes only (fixed summation order)
+// pixel chunks of the weight gradient: multiples of 256 pixels (so that
+// every step size of the kernel divides them), about 256 chunks, a function
+// of the sizes only (fixed summation order)
 long long wgrad_chunk_pix(long long npix) {
     long long c = (npix + 255) / 256;
-    c = ((c + 63) / 64) * 64;
-    return c < 64 ? 64 : c;
+    c = ((c + 255) / 256) * 256;
+    return c < 256 ? 256 : c;
 }
 
 // Device address of `scratch` on the current device, resolved once per
@@ -114,6 +115,12 @@ int nn_conv3x3_fwd(const uint16_t* x, const uint16_t* w, const float* bias, uint
     if (y32 && (y32_channels <= 0 || y32_channels > co)) return LBM_EINVAL;
     ConvArgs a{x, w, bias, y, y32, n, h, wd, ci, co, relu ? 1 : 0, y32 ? y32_channels : 0};
     return status(launch_conv_fwd(a, S(stream)));
+}
+
+int nn_set_conv_walk(int32_t steps) {
+    if (steps < 0 || steps > 64) return LBM_EINVAL;
+    set_conv_walk(steps);
+    return LBM_OK;
 }
 
 int nn_conv3x3_bwd_data(const uint16_t* dy, const uint16_t* wflip, uint16_t* dx, int32_t n, int32_t h, int32_t wd,

@@ -56,6 +56,7 @@ struct AdamArgs {
 
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st);
 hipError_t launch_conv_wgrad(const WgradArgs& a, hipStream_t st);
+void set_conv_walk(int rs);
 hipError_t launch_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dx, long long n, hipStream_t st);
 hipError_t launch_add(const uint16_t* a, const uint16_t* b, uint16_t* o, long long n, hipStream_t st);
 hipError_t launch_pool(int dir, const uint16_t* in, uint16_t* out, int n, int h, int w, int c, hipStream_t st);

@@ -198,89 +198,282 @@ __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient dW[co][t][ci] = sum_p dY[p][co] X[nbr(p, t)][ci] and bias
-// gradient, split over pixel chunks.  Block (chunk, dy) covers the three taps
-// of one neighbour row.  Per step of 64 pixels (one row segment: w % 64 == 0
-// and chunks start on multiples of 64) it stages dY once and the input row at
-// the three x shifts, both transposed to [channel][pixel] in LDS so that MFMA
-// fragments (8 consecutive pixels of one channel) are single 16-byte reads.
-// Staging uses 16-byte global loads and packs pixel pairs into 32-bit LDS
-// writes.  Wave w owns the GEMM columns (tap, 16-channel input group) w,
-// w + 4, ... for every output-channel tile: per half step it reads the dY
-// fragments once and each input fragment once for all output tiles.
-// Partial sums go to work[chunk][co][9][ci] (and work_b[chunk][co]); a second
-// kernel adds the chunks in a fixed order.
-constexpr int WG_PIX = 64;                  // pixels per step (two MFMA K=32)
-constexpr int LS = WG_PIX + 8;              // LDS row stride (bf16), 16-byte multiple
+// Row-walking convolution for rows of W = 256, 128 or 64 pixels.  A
+// work-group walks down RS consecutive steps of one image; a step is the
+// R = 256 / W output rows that its 256 pixels cover.  The work-group
+// computes CO / SPLIT of the output channels (slice blockIdx.y); per step
+// each wave owns 64 pixels of one row and CO / (SPLIT NG) of those channels
+// (NG channel groups of waves, 256 NG threads).
+//   - The weights of the work-group's channel slice, all 9 taps and CI input
+//     channels, are staged in LDS once, in MFMA fragment order (fragment
+//     (tap, K block, N tile) is 64 x 16 bytes, lane-contiguous), so a B
+//     fragment is one conflict-free 16-byte read.
+//   - The R + 2 input rows of a step sit in an LDS ring of R + 2 row slots
+//     (slot of image row r: (r + 1) mod (R + 2); rows outside the image are
+//     zeros, so taps need no bounds test).  Consecutive steps share two rows:
+//     while a step computes, the R rows the next step adds are loaded into
+//     registers, and they replace the R rows it drops after the step.
+//   - Pixel p of a row keeps each 32-channel K block in 64 bytes, four
+//     16-byte pieces; piece s sits at s ^ ((p >> 2) & 3), so the 16 lanes of
+//     an A fragment (16 consecutive pixels, one piece) hit distinct banks.
+// Arithmetic per output is the same as in the kernels above: bf16 products
+// summed in float32 over the 9 taps in order, K block by K block.
+template <int CI, int CO, int W, int NG, int SPLIT>
+__global__ __launch_bounds__(256 * NG) void conv_fwd_walk_kernel(ConvArgs a, int rs) {
+    constexpr int NTH = 256 * NG;
+    constexpr int CB = CI / 32;                  // K blocks of 32 channels
+    constexpr int COW = CO / SPLIT;              // output channels of this work-group
+    constexpr int NTT = COW / 16;                // N tiles of the work-group
+    constexpr int NT = NTT / NG;                 // N tiles of a wave
+    constexpr int R = 256 / W;                   // output rows per step
+    constexpr int NS = R + 2;                    // ring slots (input rows of a step)
+    constexpr int SLOT = CB * W * 4;             // 16-byte pieces per row slot
+    constexpr int NWF = 9 * CB * NTT * 64;       // 16-byte pieces of weights
+    constexpr int NPF = R * SLOT / NTH;          // prefetched pieces per thread
+    static_assert((R * SLOT) % NTH == 0 && NT * NG == NTT && COW % 16 == 0, "shape");
+    __shared__ uint4 s_w[NWF];
+    __shared__ uint4 s_x[NS * SLOT];
+    const int co0 = blockIdx.y * COW;            // first output channel of the slice
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wp = wave & 3, grp = wave >> 2;    // pixel quarter, channel group
+    const int kq = lane >> 4, li = lane & 15;
+    const int lr = wp / (W / 64);                // output row of this wave within a step
+    const int x0 = (wp % (W / 64)) * 64;
+    const int steps_img = a.h / R;
+    // consecutive walks share their boundary rows: give each XCD (block b runs
+    // on XCD b mod 8) a contiguous run of walks
+    const int wk = (gridDim.x % 8 == 0) ? (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3)) : (int)blockIdx.x;
+    const long long gs0 = (long long)wk * rs;                  // first global step
+    const int img = (int)(gs0 / steps_img), s0 = (int)(gs0 - (long long)img * steps_img);
+    const uint16_t* xim = a.x + (size_t)img * a.h * W * CI;
 
+    // weights of the slice: piece (co, t, c8) -> fragment (t, cb = c8 / 4,
+    // j = co / 16), lane co % 16 + 16 (c8 % 4), co counted within the slice
+    for (int q = tid; q < NWF; q += NTH) {
+        const int c8 = q % (CI / 8), rest = q / (CI / 8);
+        const int t = rest % 9, co = rest / 9;
+        const int cb = c8 >> 2, j = co >> 4;
+        s_w[((t * CB + cb) * NTT + j) * 64 + (co & 15) + 16 * (c8 & 3)] =
+            *(const uint4*)(a.wt + ((size_t)(co0 + co) * 9 + t) * CI + 8 * c8);
+    }
+    // piece q of an input row: pixel q / (4 CB), block (q / 4) % CB, piece q % 4
+    auto lds_piece = [](int q) {
+        const int px = q / (4 * CB), cb = (q >> 2) % CB, s = q & 3;
+        return (cb * W + px) * 4 + (s ^ ((px >> 2) & 3));
+    };
+    auto load_piece = [&](int row, int q) -> uint4 {
+        if (row < 0 || row >= a.h) return make_uint4(0u, 0u, 0u, 0u);
+        return *(const uint4*)(xim + ((size_t)row * W) * CI + 8 * q);   // q indexes 8-channel pieces in order
+    };
+    // first window: rows s0 R - 1 .. s0 R + R
+    for (int q = tid; q < NS * SLOT; q += NTH) {
+        const int k = q / SLOT, qq = q - k * SLOT;
+        const int row = s0 * R - 1 + k;
+        s_x[((row + 1) % NS) * SLOT + lds_piece(qq)] = load_piece(row, qq);
+    }
+    __syncthreads();
+
+    for (int st = 0; st < rs; ++st) {
+        const int s = s0 + st;
+        // prefetch the R rows the next step adds: s R + R + 1 .. s R + 2 R
+        uint4 pf[NPF];
+        if (st + 1 < rs) {
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) {
+                const int q = tid + k * NTH, rr = q / SLOT;
+                pf[k] = load_piece(s * R + R + 1 + rr, q - rr * SLOT);
+            }
+        }
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3 - 1, dx = t % 3 - 1;
+                const int row = s * R + lr + dy;
+                const uint4* xs = s_x + ((row + 1) % NS) * SLOT + cb * W * 4;
+                bf16x8 av[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int p = (x0 + 16 * m + li + dx) & (W - 1);
+                    av[m] = __builtin_bit_cast(bf16x8, xs[p * 4 + (kq ^ ((p >> 2) & 3))]);
+                }
+                const uint4* ws = s_w + ((t * CB + cb) * NTT + grp * NT) * 64 + lane;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, ws[j * 64]);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[m][j], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue: lane holds output channel co0 + 16 (grp NT + j) + li for pixels 16 m + 4 kq + r
+        const size_t prow = ((size_t)img * a.h + (size_t)s * R + lr) * W;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = co0 + 16 * (grp * NT + j) + li;
+            const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const size_t pix0 = prow + x0 + 16 * m + 4 * kq;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[m][j][r] + bias;
+                    if (a.relu) v = v > 0.f ? v : 0.f;
+                    const size_t p = pix0 + r;
+                    if (a.y16) a.y16[p * CO + co] = f2b(v);
+                    if (a.y32 && co < a.y32_ch) a.y32[p * a.y32_ch + co] = v;
+                }
+            }
+        }
+        if (st + 1 < rs) {
+            __syncthreads();                     // every wave is done with the rows dropped now
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) {
+                const int q = tid + k * NTH, rr = q / SLOT;
+                const int row = s * R + R + 1 + rr;
+                s_x[((row + 1) % NS) * SLOT + lds_piece(q - rr * SLOT)] = pf[k];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
 
-template <int CO, int CI>
-__global__ __launch_bounds__(256) void conv_wgrad_kernel(WgradArgs a) {
+// ---------------------------------------------------------------------------
+// Weight gradient dW[co][t][ci] = sum_p dY[p][co] X[nbr(p, t)][ci] and bias
+// gradient, split over pixel chunks (multiples of 256 pixels).  Block
+// (chunk, dy) covers the three taps of one neighbour row as a GEMM with
+// M = output channels, N = (tap, 16-channel input group) columns, K =
+// pixels.  It walks its chunk in steps of P pixels (256, 128 or 64,
+// dividing the row width, so a step never leaves its row); per step dY and
+// the input row at x shifts -1, 0, +1 are staged in LDS transposed to
+// [channel][pixel], so that MFMA fragments (8 consecutive pixels of one
+// channel) are single 16-byte reads.  Staging is one item per thread: an
+// octet of pixels by 8 channels (16-byte loads of the octet's 8 dY pixels,
+// or of the 10 input pixels it needs at the three shifts), transposed in
+// registers and written as 16-byte LDS stores; the next step's loads are
+// issued before the current step's MFMAs.  Wave w owns the GEMM columns w,
+// w + 4, ... for every output-channel tile: per 32-pixel half step it reads
+// the dY fragments once and each input fragment once for all output tiles.
+// Partial sums go to work[chunk][co][9][ci] (and work_b[chunk][co]); a
+// second kernel adds the chunks in a fixed order.  Bias gradient (dy = 0
+// blocks): each dY thread sums its octet over the chunk's steps, and the
+// octets are added in order at the end.
+template <int CO, int CI, int P>
+__global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
     constexpr int MT = CO / 16, NJ = CI / 16, NCOL = 3 * NJ, MAXC = (NCOL + 3) / 4;
-    __shared__ __attribute__((aligned(16))) uint16_t s_dy[CO * LS];
-    __shared__ __attribute__((aligned(16))) uint16_t s_x[3 * CI * LS];
-    const int chunk = blockIdx.x, dy = (int)blockIdx.y - 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int LP = P + 8;                    // LDS row stride (bf16), 16-byte multiple
+    constexpr int NOCT = P / 8;                  // pixel octets per step
+    constexpr int NYI = NOCT * (CO / 8), NXI = NOCT * (CI / 8);
+    static_assert(NYI + NXI <= 256, "one staging item per thread");
+    __shared__ __attribute__((aligned(16))) uint16_t s_dy[CO * LP];
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[3 * CI * LP];
+    // The three blocks of a chunk (dy = -1, 0, 1) read the same dY and
+    // overlapping input rows: they run back to back on one XCD (block b goes
+    // to XCD b mod 8), so that two of the three reads of each line hit its L2.
+    int chunk, dyi;
+    {
+        const int b = blockIdx.x;
+        if (gridDim.x % 24 == 0) {
+            const int k = b >> 3;
+            chunk = (b & 7) + 8 * (k / 3);
+            dyi = k % 3;
+        } else {
+            chunk = b / 3;
+            dyi = b % 3;
+        }
+    }
+    const int dy = dyi - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kq = lane >> 4, li = lane & 15;
+    const bool is_y = tid < NYI, is_x = !is_y && tid < NYI + NXI;
+    const int item = is_y ? tid : (is_x ? tid - NYI : 0);
+    const int oct = item % NOCT, grp = item / NOCT;          // pixel octet, 8-channel group
+    const bool want_b = a.db != nullptr && dy == 0;
     f32x4 acc[MAXC][MT];
 #pragma unroll
     for (int c = 0; c < MAXC; ++c)
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[c][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;   // bias partial of channel threadIdx.x (centre-row blocks)
+    float bpart[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) bpart[c] = 0.f;
     const long long p_begin = (long long)chunk * a.chunk_pix;
     const long long p_end = min(p_begin + a.chunk_pix, a.npix);
-    for (long long p0 = p_begin; p0 < p_end; p0 += WG_PIX) {
-        const long long rowp = p0 / a.w;               // n * h + y
+    const int nst = (int)((p_end - p_begin) / P);
+    uint4 ld[10];
+    auto issue = [&](int k) {
+        const long long p0 = p_begin + (long long)P * min(k, nst - 1);
+        const long long rowp = p0 / a.w;         // n * h + y
         const int x0 = (int)(p0 - rowp * a.w);
-        const int y = (int)(rowp % a.h);
-        const bool inb = y + dy >= 0 && y + dy < a.h;
-        const size_t xrow = (size_t)(inb ? rowp + dy : rowp) * a.w;
-        // dY: 32 pixel pairs x CO / 8 channel groups
-        for (int e = threadIdx.x; e < 32 * (CO / 8); e += 256) {
-            const int pr = e & 31, g = e >> 5, pp = 2 * pr;
-            const uint4 v0 = *(const uint4*)(a.dy + (size_t)(p0 + pp) * CO + 8 * g);
-            const uint4 v1 = *(const uint4*)(a.dy + (size_t)(p0 + pp + 1) * CO + 8 * g);
-            const uint16_t* h0 = (const uint16_t*)&v0;
-            const uint16_t* h1 = (const uint16_t*)&v1;
+        if (is_y) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) *(uint32_t*)&s_dy[(8 * g + i) * LS + pp] = pack2(h0[i], h1[i]);
-        }
-        // input row at x shifts -1, 0, +1: destination pair (pp, pp + 1) of
-        // copy dx holds source pixels x0 + pp + dx and x0 + pp + 1 + dx
-        for (int e = threadIdx.x; e < 32 * (CI / 8); e += 256) {
-            const int pr = e & 31, g = e >> 5, pp = 2 * pr;
-            uint4 v[4];
+            for (int q = 0; q < 8; ++q) ld[q] = *(const uint4*)(a.dy + (size_t)(p0 + 8 * oct + q) * CO + 8 * grp);
+        } else if (is_x) {
+            const int y = (int)(rowp % a.h);
+            const bool inb = y + dy >= 0 && y + dy < a.h;
+            const size_t xrow = (size_t)(inb ? rowp + dy : rowp) * a.w;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                int xx = x0 + pp - 1 + m;
+            for (int q = 0; q < 10; ++q) {
+                int xx = x0 + 8 * oct - 1 + q;
                 xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
-                v[m] = inb ? *(const uint4*)(a.x + (xrow + xx) * CI + 8 * g) : make_uint4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const uint16_t* hl = (const uint16_t*)&v[d];
-                const uint16_t* hh = (const uint16_t*)&v[d + 1];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) *(uint32_t*)&s_x[(d * CI + 8 * g + i) * LS + pp] = pack2(hl[i], hh[i]);
+                const uint4 v = *(const uint4*)(a.x + (xrow + xx) * CI + 8 * grp);
+                ld[q] = inb ? v : make_uint4(0u, 0u, 0u, 0u);
             }
         }
+    };
+    auto stage = [&]() {
+        if (is_y) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                uint16_t e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e[q] = ((const uint16_t*)&ld[q])[c];
+                *(uint4*)&s_dy[(8 * grp + c) * LP + 8 * oct] =
+                    make_uint4(pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7]));
+                if (want_b) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bpart[c] += b2f(e[q]);
+                }
+            }
+        } else if (is_x) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                uint16_t e[10];                  // pixels 8 oct - 1 .. 8 oct + 8 of channel 8 grp + c
+#pragma unroll
+                for (int q = 0; q < 10; ++q) e[q] = ((const uint16_t*)&ld[q])[c];
+#pragma unroll
+                for (int d = 0; d < 3; ++d)      // copy d holds pixel j + d - 1 at position j
+                    *(uint4*)&s_x[(d * CI + 8 * grp + c) * LP + 8 * oct] =
+                        make_uint4(pack2(e[d], e[d + 1]), pack2(e[d + 2], e[d + 3]), pack2(e[d + 4], e[d + 5]),
+                                   pack2(e[d + 6], e[d + 7]));
+            }
+        }
+    };
+    issue(0);
+    for (int k = 0; k < nst; ++k) {
+        stage();
+        issue(k + 1);                            // past the last step: reloads it, unused
         __syncthreads();
-        if (a.db && dy == 0 && (int)threadIdx.x < CO) {
-            for (int pp = 0; pp < WG_PIX; ++pp) bsum += b2f(s_dy[threadIdx.x * LS + pp]);
-        }
 #pragma unroll
-        for (int hf = 0; hf < WG_PIX / 32; ++hf) {
+        for (int hf = 0; hf < P / 32; ++hf) {
             bf16x8 af[MT];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) af[m] = load8(&s_dy[(16 * m + li) * LS + 32 * hf + 8 * kq]);
+            for (int m = 0; m < MT; ++m) af[m] = load8(&s_dy[(16 * m + li) * LP + 32 * hf + 8 * kq]);
 #pragma unroll
             for (int c = 0; c < MAXC; ++c) {
                 const int col = wave + 4 * c;
                 if (col < NCOL) {
                     const int d = col / NJ, nj = col - d * NJ;
-                    const bf16x8 bv = load8(&s_x[(d * CI + 16 * nj + li) * LS + 32 * hf + 8 * kq]);
+                    const bf16x8 bv = load8(&s_x[(d * CI + 16 * nj + li) * LP + 32 * hf + 8 * kq]);
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
                         acc[c][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bv, acc[c][m], 0, 0, 0);
@@ -304,7 +497,21 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgradArgs a) {
                 for (int r = 0; r < 4; ++r) wp[((size_t)(16 * m + 4 * kq + r) * 9 + t) * CI + cin] = acc[c][m][r];
         }
     }
-    if (a.db && dy == 0 && (int)threadIdx.x < CO) a.work_b[(size_t)chunk * CO + threadIdx.x] = bsum;
+    if (want_b) {
+        // octet partials through LDS (s_dy is free after the last barrier), added in octet order
+        float* s_b = (float*)s_dy;               // [grp][oct][8]
+        if (is_y) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s_b[(grp * NOCT + oct) * 8 + c] = bpart[c];
+        }
+        __syncthreads();
+        if (tid < CO) {
+            const int gq = tid >> 3, c = tid & 7;
+            float s = 0.f;
+            for (int o = 0; o < NOCT; ++o) s += s_b[(gq * NOCT + o) * 8 + c];
+            a.work_b[(size_t)chunk * CO + tid] = s;
+        }
+    }
 }
 
 // Fixed-order sum of the weight-gradient chunks.  A block owns 64
@@ -666,12 +873,66 @@ __global__ __launch_bounds__(256) void targets_kernel(const ChanDesc* desc, cons
 static inline unsigned blocks_of(long long n) { return (unsigned)((n + 255) / 256); }
 static inline bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-// The LDS-staged kernel for rows of 64, 128 or 256 pixels, except with 32
-// input and 32 output channels: there a work-group has one K block, the
+// Steps per work-group of the row-walking kernel: fixed by nn_set_conv_walk
+// (tests, tuning), else the largest of 8, 4, 2 that divides the steps of an
+// image and still leaves 256 work-groups (one per CU), else 1.
+static int g_walk_rs = 0;
+
+static int walk_steps(int steps_img, long long total) {
+    if (g_walk_rs > 0) return (steps_img % g_walk_rs == 0) ? g_walk_rs : 1;
+    for (int rs = 8; rs >= 2; rs >>= 1)
+        if (steps_img % rs == 0 && total / rs >= 256) return rs;
+    return 1;
+}
+
+template <int CI, int CO, int W, int NG, int SPLIT = 1>
+static hipError_t walk_launch(const ConvArgs& a, hipStream_t st) {
+    const int steps_img = a.h / (256 / W);
+    const long long total = (long long)a.n * steps_img;
+    const int rs = walk_steps(steps_img, total);
+    conv_fwd_walk_kernel<CI, CO, W, NG, SPLIT><<<dim3((unsigned)(total / rs), SPLIT), 256 * NG, 0, st>>>(a, rs);
+    return hipGetLastError();
+}
+
+// Row-walking kernel where it is compiled (rows of 256, 128 or 64 pixels,
+// whole steps per image, the channel pairs of the network's layers; the
+// 96-channel pairs split the output channels over two work-groups so that
+// their weights fit in LDS beside the input rows);
+// else the LDS-staged kernel for rows of 64, 128 or 256 pixels, except with
+// 32 input and 32 output channels: there a work-group has one K block, the
 // staging latency is exposed, and the unstaged kernel is faster (measured at
 // batch 32 on the network's layers: 0.075 against 0.081 ms at 256 x 128;
 // every other layer is 15-45% faster staged).
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
+    if (a.w == 256) {
+        const int key = a.ci * 1000 + a.co;
+        switch (key) {
+            case 32032: return walk_launch<32, 32, 256, 1>(a, st);
+            case 64032: return walk_launch<64, 32, 256, 1>(a, st);
+            case 32064: return walk_launch<32, 64, 256, 2>(a, st);
+            default: break;
+        }
+    }
+    if (a.w == 128 && a.h % 2 == 0) {
+        const int key = a.ci * 1000 + a.co;
+        switch (key) {
+            case 32064: return walk_launch<32, 64, 128, 2>(a, st);
+            case 64032: return walk_launch<64, 32, 128, 1>(a, st);
+            case 64064: return walk_launch<64, 64, 128, 2>(a, st);
+            case 96064: return walk_launch<96, 64, 128, 1, 2>(a, st);
+            case 64096: return walk_launch<64, 96, 128, 1, 2>(a, st);
+            default: break;
+        }
+    }
+    if (a.w == 64 && a.h % 4 == 0) {
+        const int key = a.ci * 1000 + a.co;
+        switch (key) {
+            case 64096: return walk_launch<64, 96, 64, 1, 2>(a, st);
+            case 96096: return walk_launch<96, 96, 64, 1, 2>(a, st);
+            case 96064: return walk_launch<96, 64, 64, 1, 2>(a, st);
+            default: break;
+        }
+    }
     if ((a.w == 64 || a.w == 128 || a.w == 256) && !(a.ci == 32 && a.co == 32)) {
         const int R = 256 / a.w;                 // output rows per work-group
         const unsigned grid = (unsigned)(((long long)a.n * a.h + R - 1) / R);
@@ -694,10 +955,22 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Pixels per step of the weight-gradient kernel: the largest of 256, 128, 64
+// that divides the row width and is compiled for the channel pair (256 for
+// 32 x 32, 128 up to 64 x 64), which keeps LDS at 70 KB or less.
+template <int CO, int CI, int P>
+static void wgrad2_launch(const WgradArgs& a, hipStream_t st) {
+    conv_wgrad2_kernel<CO, CI, P><<<(unsigned)(3 * a.n_chunks), 256, 0, st>>>(a);
+}
+
 template <int CO, int CI>
 static void wgrad_launch(const WgradArgs& a, hipStream_t st) {
-    conv_wgrad_kernel<CO, CI><<<dim3((unsigned)a.n_chunks, 3), 256, 0, st>>>(a);
+    if (CO == 32 && CI == 32 && a.w % 256 == 0) wgrad2_launch<CO, CI, (CO == 32 && CI == 32) ? 256 : 64>(a, st);
+    else if (CO <= 64 && CI <= 64 && a.w % 128 == 0) wgrad2_launch<CO, CI, (CO <= 64 && CI <= 64) ? 128 : 64>(a, st);
+    else wgrad2_launch<CO, CI, 64>(a, st);
 }
+
+void set_conv_walk(int rs) { g_walk_rs = rs; }
 
 hipError_t launch_conv_wgrad(const WgradArgs& a, hipStream_t st) {
     const int key = (a.co / 32) * 4 + a.ci / 32;

@@ -11,7 +11,7 @@ import ctypes
 
 from . import lbm as _lbm
 
-EXPORTS = ("nn_conv3x3_fwd", "nn_conv3x3_bwd_data", "nn_conv3x3_wgrad_workspace", "nn_conv3x3_bwd_weight",
+EXPORTS = ("nn_conv3x3_fwd", "nn_set_conv_walk", "nn_conv3x3_bwd_data", "nn_conv3x3_wgrad_workspace", "nn_conv3x3_bwd_weight",
            "nn_relu_bwd", "nn_add", "nn_pool2", "nn_up2", "nn_mse", "nn_mse_noalloc", "nn_adam", "nn_cast_weights", "nn_features",
            "nn_to_fields", "nn_targets", "nn_velocity_scale")
 
@@ -27,6 +27,7 @@ def load():
     pp = ctypes.POINTER(_lbm.lbm_params)
     L.nn_conv3x3_fwd.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, vp]
     L.nn_conv3x3_bwd_data.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp]
+    L.nn_set_conv_walk.argtypes = [i32]
     L.nn_conv3x3_wgrad_workspace.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(i64)]
     L.nn_conv3x3_bwd_weight.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i32, i32, i32, i32, vp]
     L.nn_relu_bwd.argtypes = [vp, vp, vp, i64, vp]
@@ -68,6 +69,10 @@ def _check(rc, where):
 
 def _params(cfgs):
     return (_lbm.lbm_params * len(cfgs))(*[_lbm.make_params(c) for c in cfgs])
+
+
+def nn_set_conv_walk(steps):
+    _check(load().nn_set_conv_walk(int(steps)), "nn_set_conv_walk")
 
 
 def nn_conv3x3_fwd(x, w, bias, y, y32, y32_channels, n, h, wd, ci, co, relu):

@@ -193,46 +193,48 @@ class WarmStartNet:
         h, w = hw[lev]
         nn.nn_conv3x3_bwd_data(dy, self.p[name]["wf"], dx, n, h, w, ci, co)
 
-    def backward(self, n, h, w):
-        """Parameter gradients (into gw, gb) from the output gradient in gy."""
+    def backward(self, n, h, w, probe=None):
+        """Parameter gradients (into gw, gb) from the output gradient in gy.
+        probe(name, x, dy, dx), if given, is called right after each
+        convolution's weight and data gradients, with the layer's input, the
+        output gradient it was given and the input gradient it produced (None
+        for c0), before later calls overwrite them in place."""
         B = self.bufs[(n, h, w)]
         hw = B["hw"]
-        wg, dg = self._wgrad, self._dgrad
         (h0, w0), (h1, w1), (h2, w2) = hw
-        wg("c9", B["a0"], B["gy"], n, hw)
-        dg("c9", B["gy"], B["g_a0"], n, hw)
+
+        def layer(name, x, dy, dx):
+            self._wgrad(name, x, dy, n, hw)
+            if dx is not None:
+                self._dgrad(name, dy, dx, n, hw)
+            if probe is not None:
+                probe(name, x, dy, dx)
+
+        layer("c9", B["a0"], B["gy"], B["g_a0"])
         nn.nn_relu_bwd(B["g_a0"], B["c8"], B["G8"])
-        wg("c8", B["u0"], B["G8"], n, hw)
-        dg("c8", B["G8"], B["g_u0"], n, hw)
+        layer("c8", B["u0"], B["G8"], B["g_u0"])
         nn.nn_up2(1, B["g_u0"], B["g_c7"], n, h1, w1, 64)
         nn.nn_relu_bwd(B["g_c7"], B["c7"], B["g_c7"])
-        wg("c7", B["a1"], B["g_c7"], n, hw)
-        dg("c7", B["g_c7"], B["g_a1"], n, hw)
+        layer("c7", B["a1"], B["g_c7"], B["g_a1"])
         nn.nn_relu_bwd(B["g_a1"], B["c6"], B["G6"])
-        wg("c6", B["u1"], B["G6"], n, hw)
-        dg("c6", B["G6"], B["g_u1"], n, hw)
+        layer("c6", B["u1"], B["G6"], B["g_u1"])
         nn.nn_up2(1, B["g_u1"], B["g_c5"], n, h2, w2, 96)
         nn.nn_relu_bwd(B["g_c5"], B["c5"], B["g_c5"])
-        wg("c5", B["c4"], B["g_c5"], n, hw)
-        dg("c5", B["g_c5"], B["g_c4"], n, hw)
+        layer("c5", B["c4"], B["g_c5"], B["g_c4"])
         nn.nn_relu_bwd(B["g_c4"], B["c4"], B["g_c4"])
-        wg("c4", B["p1"], B["g_c4"], n, hw)
-        dg("c4", B["g_c4"], B["g_p1"], n, hw)
+        layer("c4", B["p1"], B["g_c4"], B["g_p1"])
         nn.nn_pool2(1, B["g_p1"], B["tmp1"], n, h1, w1, 64)
         nn.nn_add(B["g_a1"], B["tmp1"], B["g_a1"])                   # grad of s1 = c3
         nn.nn_relu_bwd(B["g_a1"], B["c3"], B["g_a1"])
-        wg("c3", B["c2"], B["g_a1"], n, hw)
-        dg("c3", B["g_a1"], B["g_c2"], n, hw)
+        layer("c3", B["c2"], B["g_a1"], B["g_c2"])
         nn.nn_relu_bwd(B["g_c2"], B["c2"], B["g_c2"])
-        wg("c2", B["p0"], B["g_c2"], n, hw)
-        dg("c2", B["g_c2"], B["g_p0"], n, hw)
+        layer("c2", B["p0"], B["g_c2"], B["g_p0"])
         nn.nn_pool2(1, B["g_p0"], B["tmp0"], n, h0, w0, 32)
         nn.nn_add(B["g_a0"], B["tmp0"], B["g_a0"])                   # grad of s0 = c1
         nn.nn_relu_bwd(B["g_a0"], B["c1"], B["g_a0"])
-        wg("c1", B["c0"], B["g_a0"], n, hw)
-        dg("c1", B["g_a0"], B["g_c0"], n, hw)
+        layer("c1", B["c0"], B["g_a0"], B["g_c0"])
         nn.nn_relu_bwd(B["g_c0"], B["c0"], B["g_c0"])
-        wg("c0", B["x"], B["g_c0"], n, hw)
+        layer("c0", B["x"], B["g_c0"], None)
 
     def loss_grad(self, target, n, h, w):
         """MSE of the last forward output against target [n][h][w][4];

@@ -4,9 +4,8 @@
 Bounds: float32 outputs of a convolution agree to 2e-5 of the output scale
 (float32 accumulation of bf16 products); bf16 outputs to one bf16 rounding
 (2^-8 relative) plus that; weight gradients (float32) to 2e-5 of their
-scale.  The whole-network gradient check compares every layer's weight
-gradient in relative 2-norm; activations and their gradients are stored in
-bf16 between layers, so the bound there is 3e-2."""
+scale.  The whole network is checked layer by layer, each layer on the bf16
+values the GPU stored for it, with the same per-element bounds."""
 import numpy as np
 import pytest
 
@@ -79,6 +78,38 @@ def test_conv_forward_row_widths(env, n, h, w, ci, co):
     assert np.max(np.abs(host(y32) - ref)) <= 2e-5 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("ci,co,w", [(32, 32, 256), (64, 32, 256), (32, 64, 256), (32, 64, 128), (64, 32, 128),
+                                     (64, 64, 128), (96, 64, 128), (64, 96, 128), (64, 96, 64), (96, 96, 64),
+                                     (96, 64, 64)])
+@pytest.mark.parametrize("rs", [1, 2, 8])
+def test_conv_forward_row_walk(env, ci, co, w, rs):
+    """The row-walking kernel (rows of 256, 128 and 64 pixels, every channel
+    pair it is compiled for, the 96-channel pairs with their output channels
+    split over two work-groups) with 1, 2 and 8 steps per work-group: 3
+    images of 8 steps, so the walks start at image boundaries and the
+    input-row ring turns over; bias and ReLU, bf16 and float32 outputs."""
+    torch, nn = env
+    R = 256 // w
+    n, h = 3, 8 * R
+    rng = np.random.default_rng(1000 * rs + ci + co + w)
+    x, xr = bf(torch, rng.normal(size=(n, h, w, ci)))
+    wt, wr = bf(torch, rng.normal(size=(co, 9, ci)) / np.sqrt(9 * ci))
+    b = rng.normal(size=co).astype(np.float32)
+    y16 = torch.empty((n, h, w, co), dtype=torch.bfloat16, device="cuda")
+    y32 = torch.empty((n, h, w, co), dtype=torch.float32, device="cuda")
+    print("case: walk ci %d co %d w %d steps %d" % (ci, co, w, rs), flush=True)
+    nn.nn_set_conv_walk(rs)
+    try:
+        nn.nn_conv3x3_fwd(x, wt, f32(torch, b), y16, y32, co, n, h, w, ci, co, 1)
+        torch.cuda.synchronize()
+    finally:
+        nn.nn_set_conv_walk(0)
+    ref = O.relu(O.conv3x3(xr, wr, b.astype(np.float64)))
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(host(y32) - ref)) <= 2e-5 * scale
+    assert np.all(np.abs(host(y16) - ref) <= 2.0 ** -8 * np.abs(ref) + 2e-5 * scale)
+
+
 @pytest.mark.parametrize("ci,co", [(32, 32), (64, 96), (96, 64)])
 def test_conv_backward(env, ci, co):
     torch, nn = env
@@ -106,6 +137,35 @@ def test_conv_backward(env, ci, co):
     # accumulate mode adds
     nn.nn_conv3x3_bwd_weight(x, dy, dw, db, work, 1, n, h, w, ci, co)
     assert np.max(np.abs(host(dw) - 2 * rdw)) <= 4e-5 * np.max(np.abs(rdw))
+
+
+@pytest.mark.parametrize("n,h,w,ci,co", [
+    (2, 160, 256, 32, 32),   # 256-pixel steps, two per chunk
+    (1, 96, 256, 64, 32),    # 128-pixel steps in 256-pixel rows
+    (2, 130, 128, 64, 64),   # 128-pixel steps, two per chunk
+    (1, 40, 64, 96, 96),     # 64-pixel steps, four per chunk
+    (2, 3, 192, 32, 32),     # a width outside 64 / 128 / 256: 64-pixel steps, short last chunk
+])
+def test_conv_weight_gradient_step_sizes(env, n, h, w, ci, co):
+    """The weight gradient at every step size its kernel uses, with chunks
+    of several steps and a short last chunk: dw and db against the oracle,
+    and accumulate mode."""
+    torch, nn = env
+    rng = np.random.default_rng(n * h * w + 3 * ci + co)
+    x, xr = bf(torch, rng.normal(size=(n, h, w, ci)))
+    dy, dyr = bf(torch, rng.normal(size=(n, h, w, co)))
+    wr = np.zeros((co, 9, ci))
+    rdx, rdw, rdb = O.conv3x3_backward(xr, wr, dyr)
+    dw = torch.empty((co, 9, ci), dtype=torch.float32, device="cuda")
+    db = torch.empty(co, dtype=torch.float32, device="cuda")
+    work = torch.empty(nn.nn_conv3x3_wgrad_workspace(n, h, w, ci, co), dtype=torch.uint8, device="cuda")
+    print("case: wgrad n %d h %d w %d ci %d co %d" % (n, h, w, ci, co), flush=True)
+    nn.nn_conv3x3_bwd_weight(x, dy, dw, db, work, 0, n, h, w, ci, co)
+    assert np.max(np.abs(host(dw) - rdw)) <= 2e-5 * np.max(np.abs(rdw))
+    assert np.max(np.abs(host(db) - rdb)) <= 2e-5 * np.max(np.abs(rdb))
+    nn.nn_conv3x3_bwd_weight(x, dy, dw, db, work, 1, n, h, w, ci, co)
+    assert np.max(np.abs(host(dw) - 2 * rdw)) <= 4e-5 * np.max(np.abs(rdw))
+    assert np.max(np.abs(host(db) - 2 * rdb)) <= 4e-5 * np.max(np.abs(rdb))
 
 
 @pytest.mark.parametrize("n,h,w,c", [(3, 4, 256, 96), (1, 2, 128, 64)])
@@ -278,10 +338,30 @@ def test_features_targets_and_handoff(env):
             assert np.array_equal(lbm.lbm_get_state(a, k), lbm.lbm_get_state(b, k))
 
 
+# inputs of each convolution and the layer whose output feeds it (forward)
+FWD_IN = {"c0": "x", "c1": "c0", "c2": "p0", "c3": "c2", "c4": "p1", "c5": "c4", "c6": "u1", "c7": "a1",
+          "c8": "u0", "c9": "a0"}
+
+
+def bf16_close(got, ref, scale):
+    """Within one bfloat16 rounding of ref, plus float32 accumulation slack."""
+    return np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 2e-5 * scale)
+
+
 def test_network_gradients_against_oracle(env):
-    """Whole U-Net, batch of 2 channels of 8 x 256: loss and every layer's
-    weight and bias gradient against the float64 oracle evaluated with the
-    network's bf16 weights and inputs."""
+    """Whole U-Net, batch of 2 channels of 8 x 256, checked layer by layer
+    and element by element against the float64 oracle, each layer on the
+    very bf16 values the GPU gave it:
+      forward: every convolution's output against the oracle convolution of
+        its stored input with the bf16 weights (one bf16 rounding), and every
+        pooling, upsampling and skip addition between them;
+      backward: every layer's weight and bias gradients (float32, 2e-5 of
+        their scale) and input gradient (one bf16 rounding) against the
+        oracle's conv3x3_backward of its stored input and output gradient,
+        and every output gradient a layer was given against the oracle chain
+        rule (ReLU mask, upsampling and pooling adjoints, skip sums) applied
+        to the GPU's own upstream gradients;
+    and the loss against the oracle's."""
     torch, nn = env
     from paper_2210_07501_amd import warmstart as ws
     net = ws.WarmStartNet(seed=3)
@@ -294,22 +374,73 @@ def test_network_gradients_against_oracle(env):
     x[..., :10] = torch.from_numpy(rng.normal(size=(n, h, w, 10)).astype(np.float32)).cuda().to(torch.bfloat16)
     tgt = rng.normal(size=(n, h, w, 4)).astype(np.float32)
     net.forward(x, n, h, w)
+    B = net.bufs[(n, h, w)]
+    A = {k: host(B[k]) for k in ("x", "c0", "c1", "p0", "c2", "c3", "p1", "c4", "c5", "u1", "c6", "a1", "c7", "u0",
+                                 "c8", "a0")}
+    y32 = B["y32"].cpu().numpy().astype(np.float64)
+    Wt = {name: host(net.p[name]["w16"]) for name in ws.LAYERS}
+    bias = {name: net.p[name]["b"].cpu().numpy().astype(np.float64) for name in ws.LAYERS}
+    # forward, layer by layer
+    for name in ws.LAYERS:
+        ref = O.conv3x3(A[FWD_IN[name]], Wt[name], bias[name])
+        if name == "c9":
+            ref = ref[..., :ws.NOUT]
+            assert np.max(np.abs(y32 - ref)) <= 2e-5 * np.max(np.abs(ref)), name
+        else:
+            ref = O.relu(ref)
+            assert bf16_close(A[name], ref, np.max(np.abs(ref))), name
+    for out, ref in (("p0", O.pool2(A["c1"])), ("p1", O.pool2(A["c3"])), ("u1", O.up2(A["c5"])),
+                     ("u0", O.up2(A["c7"])), ("a1", A["c6"] + A["c3"]), ("a0", A["c8"] + A["c1"])):
+        assert bf16_close(A[out], ref, np.max(np.abs(ref))), out
     loss = float(net.loss_grad(f32(torch, tgt), n, h, w).cpu()[0])
-    net.backward(n, h, w)
+    gy = host(B["gy"])
+    seen = {}
+    net.backward(n, h, w, probe=lambda name, X, DY, DX: seen.__setitem__(
+        name, (host(X), host(DY), None if DX is None else host(DX))))
+    # the loss and its gradient
     p = {}
     for name in ws.LAYERS:
-        p[name + ".w"] = host(net.p[name]["w16"])
-        p[name + ".b"] = net.p[name]["b"].cpu().numpy().astype(np.float64)
-    ref_loss, g, _ = O.loss_and_grads(p, host(x), tgt.astype(np.float64), 4)
+        p[name + ".w"], p[name + ".b"] = Wt[name], bias[name]
+    ref_loss, _, _ = O.loss_and_grads(p, A["x"], tgt.astype(np.float64), 4)
     print("loss gpu %.6e oracle %.6e" % (loss, ref_loss), flush=True)
     assert loss == pytest.approx(ref_loss, rel=1e-2)
+    l_y, d_y = O.mse(y32, tgt.astype(np.float64))
+    assert loss == pytest.approx(l_y, rel=1e-6)
+    ref_gy = np.zeros_like(gy)
+    ref_gy[..., :4] = d_y
+    assert bf16_close(gy, ref_gy, np.max(np.abs(ref_gy)))
+    assert np.all(gy[..., 4:] == 0)
+    # each layer's own gradients, on the inputs it was given
     for name in ws.LAYERS:
-        gw = net.p[name]["gw"].cpu().numpy()
-        gb = net.p[name]["gb"].cpu().numpy()
-        ew = np.linalg.norm(gw - g[name + ".w"]) / np.linalg.norm(g[name + ".w"])
-        eb = np.linalg.norm(gb - g[name + ".b"]) / max(np.linalg.norm(g[name + ".b"]), 1e-30)
-        print("layer %s: weight-gradient error %.2e, bias %.2e" % (name, ew, eb), flush=True)
-        assert ew <= 3e-2 and eb <= 3e-2, name
+        X, DY, DX = seen[name]
+        assert np.array_equal(X, A[FWD_IN[name]]), name
+        rdx, rdw, rdb = O.conv3x3_backward(X, Wt[name], DY)
+        gw = net.p[name]["gw"].cpu().numpy().astype(np.float64)
+        gb = net.p[name]["gb"].cpu().numpy().astype(np.float64)
+        ew = np.max(np.abs(gw - rdw)) / np.max(np.abs(rdw))
+        eb = np.max(np.abs(gb - rdb)) / max(np.max(np.abs(rdb)), 1e-30)
+        print("layer %s: weight-gradient max error / scale %.2e, bias %.2e" % (name, ew, eb), flush=True)
+        assert ew <= 2e-5 and eb <= 2e-5, name
+        if DX is not None:
+            assert bf16_close(DX, rdx, np.max(np.abs(rdx))), name
+    # the output gradient each layer was given: the chain rule on the GPU's own upstream gradients
+    dx = {name: seen[name][2] for name in ws.LAYERS}
+    relu_b = lambda g, out: g * (out > 0)
+    chain = {
+        "c9": ref_gy,
+        "c8": relu_b(dx["c9"], A["c8"]),
+        "c7": relu_b(O.up2_backward(dx["c8"]), A["c7"]),
+        "c6": relu_b(dx["c7"], A["c6"]),
+        "c5": relu_b(O.up2_backward(dx["c6"]), A["c5"]),
+        "c4": relu_b(dx["c5"], A["c4"]),
+        "c3": relu_b(dx["c7"] + O.pool2_backward(dx["c4"]), A["c3"]),
+        "c2": relu_b(dx["c3"], A["c2"]),
+        "c1": relu_b(dx["c9"] + O.pool2_backward(dx["c2"]), A["c1"]),
+        "c0": relu_b(dx["c1"], A["c0"]),
+    }
+    for name in ws.LAYERS:
+        ref = chain[name]
+        assert bf16_close(seen[name][1], ref, np.max(np.abs(ref))), name
 
 
 def test_training_reduces_loss(env):

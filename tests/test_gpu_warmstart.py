@@ -8,9 +8,11 @@ interface band, shifted so that sum phi is the cold start's; channels
 whose float32 residual levels off above the tolerance are finished in
 float64.  Checked: the network's raw errors are far below those of the
 state at rest; every channel converges from both starts and ends in the
-same steady state; it needs at least 10% fewer steps in total over the
-channels both converge on (measured here: 21%; on 256 held-out channels:
-median 88 301 against 120 751 steps, per-channel median ratio 1.33).  The
+same steady state; it needs at least 15% fewer steps in total over the
+channels both converge on (measured here: 16%, cold / warm 1.19) and a
+per-channel median step ratio cold / warm of at least 1.2 (measured here:
+1.30; on all 256 held-out channels:
+median 87 401 against 121 601 steps, per-channel median ratio 1.33).  The
 remaining steps are set
 by the slow viscous, thermal and interface modes, which a prediction a few
 percent off shortens only logarithmically.
@@ -60,7 +62,8 @@ def test_warm_start_saves_steps_and_reaches_the_same_state(env):
     both = conv_w & conv_c
     print("cold / warm steps: total %.3f, per channel %s" % (sc[both].sum() / sw[both].sum(),
           np.round(sc / sw, 2).tolist()), flush=True)
-    assert sw[both].sum() <= 0.9 * sc[both].sum()
+    assert sw[both].sum() <= 0.85 * sc[both].sum()
+    assert np.median(sc[both] / sw[both]) >= 1.2
     Fw = ws.fields_tensor(ctx_w, N)
     Fc = ws.fields_tensor(ctx_c, N)
     err = ws.relative_errors(Fw, Fc)
