@@ -430,31 +430,34 @@ __global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
             }
         }
     };
+    // transposes with byte permutes: word (lo, hi) = half c & 1 of dword
+    // c >> 1 of pixel lo and of pixel hi
+    auto word = [](const uint4& lo, const uint4& hi, int c) -> uint32_t {
+        const uint32_t a = ((const uint32_t*)&lo)[c >> 1], b = ((const uint32_t*)&hi)[c >> 1];
+        return __builtin_amdgcn_perm(b, a, (c & 1) ? 0x07060302u : 0x05040100u);
+    };
     auto stage = [&]() {
         if (is_y) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                uint16_t e[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) e[q] = ((const uint16_t*)&ld[q])[c];
                 *(uint4*)&s_dy[(8 * grp + c) * LP + 8 * oct] =
-                    make_uint4(pack2(e[0], e[1]), pack2(e[2], e[3]), pack2(e[4], e[5]), pack2(e[6], e[7]));
+                    make_uint4(word(ld[0], ld[1], c), word(ld[2], ld[3], c), word(ld[4], ld[5], c), word(ld[6], ld[7], c));
                 if (want_b) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) bpart[c] += b2f(e[q]);
+                    for (int q = 0; q < 8; ++q) bpart[c] += b2f(((const uint16_t*)&ld[q])[c]);
                 }
             }
         } else if (is_x) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                uint16_t e[10];                  // pixels 8 oct - 1 .. 8 oct + 8 of channel 8 grp + c
-#pragma unroll
-                for (int q = 0; q < 10; ++q) e[q] = ((const uint16_t*)&ld[q])[c];
-#pragma unroll
-                for (int d = 0; d < 3; ++d)      // copy d holds pixel j + d - 1 at position j
-                    *(uint4*)&s_x[(d * CI + 8 * grp + c) * LP + 8 * oct] =
-                        make_uint4(pack2(e[d], e[d + 1]), pack2(e[d + 2], e[d + 3]), pack2(e[d + 4], e[d + 5]),
-                                   pack2(e[d + 6], e[d + 7]));
+                // ld[q] holds pixel 8 oct - 1 + q; copy d holds pixel j + d - 1 at position j
+                const uint32_t e01 = word(ld[0], ld[1], c), e23 = word(ld[2], ld[3], c), e45 = word(ld[4], ld[5], c),
+                               e67 = word(ld[6], ld[7], c), e89 = word(ld[8], ld[9], c);
+                const uint32_t e12 = word(ld[1], ld[2], c), e34 = word(ld[3], ld[4], c), e56 = word(ld[5], ld[6], c),
+                               e78 = word(ld[7], ld[8], c);
+                *(uint4*)&s_x[(0 * CI + 8 * grp + c) * LP + 8 * oct] = make_uint4(e01, e23, e45, e67);
+                *(uint4*)&s_x[(1 * CI + 8 * grp + c) * LP + 8 * oct] = make_uint4(e12, e34, e56, e78);
+                *(uint4*)&s_x[(2 * CI + 8 * grp + c) * LP + 8 * oct] = make_uint4(e23, e45, e67, e89);
             }
         }
     };
@@ -955,9 +958,11 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Pixels per step of the weight-gradient kernel: the largest of 256, 128, 64
-// that divides the row width and is compiled for the channel pair (256 for
-// 32 x 32, 128 up to 64 x 64), which keeps LDS at 70 KB or less.
+// Pixels per step of the weight-gradient kernel: 128 where the row width
+// allows it and the block's LDS, (CO + 3 CI)(P + 8) bf16, stays within
+// 53 KB, else 64.  Three blocks then fit on a CU (registers allow three
+// too), so the 3 x 256 blocks of a layer are resident at once instead of
+// running in one and a half rounds.
 template <int CO, int CI, int P>
 static void wgrad2_launch(const WgradArgs& a, hipStream_t st) {
     conv_wgrad2_kernel<CO, CI, P><<<(unsigned)(3 * a.n_chunks), 256, 0, st>>>(a);
@@ -965,8 +970,8 @@ static void wgrad2_launch(const WgradArgs& a, hipStream_t st) {
 
 template <int CO, int CI>
 static void wgrad_launch(const WgradArgs& a, hipStream_t st) {
-    if (CO == 32 && CI == 32 && a.w % 256 == 0) wgrad2_launch<CO, CI, (CO == 32 && CI == 32) ? 256 : 64>(a, st);
-    else if (CO <= 64 && CI <= 64 && a.w % 128 == 0) wgrad2_launch<CO, CI, (CO <= 64 && CI <= 64) ? 128 : 64>(a, st);
+    constexpr bool P128 = (CO + 3 * CI) * (128 + 8) * 2 <= 53 * 1024;
+    if (P128 && a.w % 128 == 0) wgrad2_launch<CO, CI, P128 ? 128 : 64>(a, st);
     else wgrad2_launch<CO, CI, 64>(a, st);
 }
 

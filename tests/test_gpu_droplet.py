@@ -5,7 +5,7 @@ Domain 8R x 16R with R = 20, uniform temperature gradient 0.1 between the
 walls, mu = k = 0.2, sigma_T = -1e-4.  The paper compares its 2D droplet with
 the 3D Young-Goldstein-Block velocity U_YGB = 1.333e-4 and finds about 80% of
 it (as do the other 2D schemes it cites).  Checked: the droplet moves toward
-the hot wall at a terminal velocity within [0.75, 0.85] U_YGB (measured 0.77),
+the hot wall at a terminal velocity within [0.75, 0.85] U_YGB (measured 0.791),
 keeps sum phi (float64: 1e-12; float32: 1e-7 over 1e5 steps), and float32
 agrees with float64; a smaller droplet matches the float64 oracle step by
 step (curvature and its stencils)."""
