@@ -115,3 +115,8 @@ def test_network_calls_reject_bad_shapes():
     # elementwise: negative counts
     assert L.nn_add(p, p, p, -1, None) == E
     assert L.nn_relu_bwd(p, p, p, -1, None) == E
+    # the row-walking tuning knob: 0 (automatic) to 64 steps per work-group
+    assert L.nn_set_conv_walk(-1) == E
+    assert L.nn_set_conv_walk(65) == E
+    assert L.nn_set_conv_walk(8) == lbm.LBM_OK
+    assert L.nn_set_conv_walk(0) == lbm.LBM_OK
