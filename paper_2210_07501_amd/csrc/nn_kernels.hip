@@ -878,21 +878,33 @@ static inline bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Steps per work-group of the row-walking kernel: fixed by nn_set_conv_walk
 // (tests, tuning), else the largest of 8, 4, 2 that divides the steps of an
-// image and still leaves 256 work-groups (one per CU), else 1.
+// image and still leaves one round of work-groups, as many as the CUs hold
+// at once (256 CUs times the work-groups that fit on one CU, from the
+// runtime's occupancy query: LDS and registers), else 1.  Longer walks share
+// more input rows and stage the weights fewer times.
 static int g_walk_rs = 0;
 
-static int walk_steps(int steps_img, long long total) {
+static int walk_steps(int steps_img, long long groups, int per_cu) {
     if (g_walk_rs > 0) return (steps_img % g_walk_rs == 0) ? g_walk_rs : 1;
     for (int rs = 8; rs >= 2; rs >>= 1)
-        if (steps_img % rs == 0 && total / rs >= 256) return rs;
+        if (steps_img % rs == 0 && groups / rs >= 256LL * per_cu) return rs;
     return 1;
 }
 
 template <int CI, int CO, int W, int NG, int SPLIT = 1>
 static hipError_t walk_launch(const ConvArgs& a, hipStream_t st) {
-    const int steps_img = a.h / (256 / W);
+    constexpr int R = 256 / W;
+    static int per_cu = 0;                       // resident work-groups per CU, queried once
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, conv_fwd_walk_kernel<CI, CO, W, NG, SPLIT>, 256 * NG, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int steps_img = a.h / R;
     const long long total = (long long)a.n * steps_img;
-    const int rs = walk_steps(steps_img, total);
+    const int rs = walk_steps(steps_img, total * SPLIT, per_cu);
     conv_fwd_walk_kernel<CI, CO, W, NG, SPLIT><<<dim3((unsigned)(total / rs), SPLIT), 256 * NG, 0, st>>>(a, rs);
     return hipGetLastError();
 }
