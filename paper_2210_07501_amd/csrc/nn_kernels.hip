@@ -975,13 +975,36 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
 // else 64.  Measured on the network's layers at batch 32, 128-pixel steps
 // beat 64-pixel ones even where they leave fewer blocks per CU (32 x 64:
 // 0.187 against 0.232 ms; 64 x 64: 0.063 against 0.089 ms).
+// The chunk count is cut, where that helps, to what one round of resident
+// blocks covers (three blocks per chunk; 256 CUs times the blocks that fit
+// on one, from the runtime's occupancy query), rounded down to a multiple of
+// 8: a layer whose blocks do not all fit at once would otherwise run one and
+// a half rounds.  Fewer, longer chunks fit in the workspace sized for the
+// default count; the sum stays deterministic (a function of the sizes and
+// the kernel).
 template <int CO, int CI, int P>
-static void wgrad2_launch(const WgradArgs& a, hipStream_t st) {
+static void wgrad2_launch(WgradArgs& a, hipStream_t st) {
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, conv_wgrad2_kernel<CO, CI, P>, 256, 0) != hipSuccess ||
+            nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const long long want = (256LL * per_cu / 3) / 8 * 8;
+    if (want >= 8 && want < a.n_chunks) {
+        long long cp = (a.npix + want - 1) / want;
+        cp = ((cp + 255) / 256) * 256;
+        a.chunk_pix = cp;
+        a.n_chunks = (int)((a.npix + cp - 1) / cp);
+        a.work_b = a.work + (size_t)a.n_chunks * CO * 9 * CI;
+    }
     conv_wgrad2_kernel<CO, CI, P><<<(unsigned)(3 * a.n_chunks), 256, 0, st>>>(a);
 }
 
 template <int CO, int CI>
-static void wgrad_launch(const WgradArgs& a, hipStream_t st) {
+static void wgrad_launch(WgradArgs& a, hipStream_t st) {
     constexpr bool P128 = CO <= 64 && CI <= 64;
     if (P128 && a.w % 128 == 0) wgrad2_launch<CO, CI, P128 ? 128 : 64>(a, st);
     else wgrad2_launch<CO, CI, 64>(a, st);
@@ -989,7 +1012,8 @@ static void wgrad_launch(const WgradArgs& a, hipStream_t st) {
 
 void set_conv_walk(int rs) { g_walk_rs = rs; }
 
-hipError_t launch_conv_wgrad(const WgradArgs& a, hipStream_t st) {
+hipError_t launch_conv_wgrad(const WgradArgs& args, hipStream_t st) {
+    WgradArgs a = args;                          // the launch may choose longer chunks
     const int key = (a.co / 32) * 4 + a.ci / 32;
     switch (key) {
         case 1 * 4 + 1: wgrad_launch<32, 32>(a, st); break;

@@ -145,10 +145,12 @@ def test_conv_backward(env, ci, co):
     (2, 130, 128, 64, 64),   # 128-pixel steps, two per chunk
     (1, 40, 64, 96, 96),     # 64-pixel steps, four per chunk
     (2, 3, 192, 32, 32),     # a width outside 64 / 128 / 256: 64-pixel steps, short last chunk
+    (1, 256, 256, 64, 32),   # 256 default chunks, cut to one round of resident blocks
 ])
 def test_conv_weight_gradient_step_sizes(env, n, h, w, ci, co):
     """The weight gradient at every step size its kernel uses, with chunks
-    of several steps and a short last chunk: dw and db against the oracle,
+    of several steps and a short last chunk, and with the chunk count cut to
+    what one round of resident blocks covers: dw and db against the oracle,
     and accumulate mode."""
     torch, nn = env
     rng = np.random.default_rng(n * h * w + 3 * ci + co)
