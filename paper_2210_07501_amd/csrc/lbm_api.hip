@@ -177,12 +177,15 @@ int tiles_of(const lbm_params& p, int tx, int ty, int* tiles_x) {
 }
 
 // Tile layout of a channel: tiles_x, tiles_y and the strip width (in tiles).
-// Eight strips across the channel: a channel that fills the GPU hands one
-// strip to each of the eight XCDs.
-void set_layout(Inst& I, const lbm_params& p, int tx, int ty) {
+// Float32: eight strips across the channel, so that a channel that fills the
+// GPU hands one full-height strip to each of the eight XCDs.  Float64: four
+// strips, each XCD taking half of one (measured on 4096 x 2048: 1.2% faster
+// and 3% fewer HBM reads than eight strips in float64, 4% slower in float32).
+void set_layout(Inst& I, const lbm_params& p, int tx, int ty, int prec) {
     I.tiles_x = (p.nx + tx - 1) / tx;
     I.tiles_y = (p.ny + ty - 1) / ty;
-    I.strip_w = std::max(1, (I.tiles_x + 7) / 8);
+    const int strips = prec == LBM_FP64 ? 4 : 8;
+    I.strip_w = std::max(1, (I.tiles_x + strips - 1) / strips);
 }
 
 // Build the tile table for the current tile shape over the channels whose
@@ -191,7 +194,7 @@ int build_tiles(lbm_ctx* c, bool all) {
     c->h_tile_inst.clear();
     for (int k = 0; k < c->n_inst; ++k) {
         int nt = tiles_of(c->params[k], c->tx, c->ty, nullptr);
-        set_layout(c->h_inst[k], c->params[k], c->tx, c->ty);
+        set_layout(c->h_inst[k], c->params[k], c->tx, c->ty, c->prec);
         c->h_inst[k].ntiles = nt;
         c->h_inst[k].tile0 = (int)c->h_tile_inst.size();
         if (all || !c->retired[k]) {
@@ -938,7 +941,7 @@ int lbm_fields(lbm_ctx* c, int32_t inst, double* phi, double* ux, double* uy, do
     int nt = tiles_of(P, c->tx, c->ty, &txs);
     Inst I = c->h_inst[inst];
     I.tile0 = 0;
-    set_layout(I, P, c->tx, c->ty);
+    set_layout(I, P, c->tx, c->ty, c->prec);
     I.ntiles = nt;
     I.active = 1;
     Inst* dI = (Inst*)dev_alloc(c, sizeof(Inst));
