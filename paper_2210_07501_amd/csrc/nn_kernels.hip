@@ -909,21 +909,23 @@ static hipError_t walk_launch(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Row-walking kernel where it is compiled (rows of 256, 128 or 64 pixels,
-// whole steps per image, the channel pairs of the network's layers; the
-// 96-channel pairs split the output channels over two work-groups so that
-// their weights fit in LDS beside the input rows);
-// else the LDS-staged kernel for rows of 64, 128 or 256 pixels, except with
-// 32 input and 32 output channels: there a work-group has one K block, the
-// staging latency is exposed, and the unstaged kernel is faster (measured at
-// batch 32 on the network's layers: 0.075 against 0.081 ms at 256 x 128;
-// every other layer is 15-45% faster staged).
+// Row-walking kernel where it is compiled: rows of 256, 128 or 64 pixels,
+// whole steps per image, the channel pairs of the network's layers.  The
+// unsplit layers run 512-thread work-groups of two channel groups (measured
+// 2-10% faster than one group for the 32-channel outputs at batch 32); the
+// 96-channel pairs split their output channels over two work-groups so that
+// their weights fit in LDS beside the input rows.  Other shapes take the
+// LDS-staged kernel for rows of 64, 128 or 256 pixels, except with 32 input
+// and 32 output channels: there a work-group has one K block, the staging
+// latency is exposed, and the unstaged kernel is faster (measured at batch
+// 32 on the network's layers: 0.075 against 0.081 ms at 256 x 128; every
+// other layer is 15-45% faster staged).
 hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
     if (a.w == 256) {
         const int key = a.ci * 1000 + a.co;
         switch (key) {
-            case 32032: return walk_launch<32, 32, 256, 1>(a, st);
-            case 64032: return walk_launch<64, 32, 256, 1>(a, st);
+            case 32032: return walk_launch<32, 32, 256, 2>(a, st);
+            case 64032: return walk_launch<64, 32, 256, 2>(a, st);
             case 32064: return walk_launch<32, 64, 256, 2>(a, st);
             default: break;
         }
@@ -932,7 +934,7 @@ hipError_t launch_conv_fwd(const ConvArgs& a, hipStream_t st) {
         const int key = a.ci * 1000 + a.co;
         switch (key) {
             case 32064: return walk_launch<32, 64, 128, 2>(a, st);
-            case 64032: return walk_launch<64, 32, 128, 1>(a, st);
+            case 64032: return walk_launch<64, 32, 128, 2>(a, st);
             case 64064: return walk_launch<64, 64, 128, 2>(a, st);
             case 96064: return walk_launch<96, 64, 128, 1, 2>(a, st);
             case 64096: return walk_launch<64, 96, 128, 1, 2>(a, st);
