@@ -371,7 +371,10 @@ template <int CO, int CI, int P>
 __global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
     constexpr int MT = CO / 16, NJ = CI / 16, NCOL = 3 * NJ, MAXC = (NCOL + 3) / 4;
     constexpr int LP = P + 8;                    // LDS row stride (bf16), 16-byte multiple
-    constexpr int NOCT = P / 8;                  // pixel octets per step
+    // staging item: Q pixels by 8 channels; quartets where they give every
+    // thread an item, else octets
+    constexpr int Q = ((P / 4) * ((CO + CI) / 8) <= 256) ? 4 : 8;
+    constexpr int NOCT = P / Q;                  // pixel groups per step
     constexpr int NYI = NOCT * (CO / 8), NXI = NOCT * (CI / 8);
     static_assert(NYI + NXI <= 256, "one staging item per thread");
     __shared__ __attribute__((aligned(16))) uint16_t s_dy[CO * LP];
@@ -394,9 +397,12 @@ __global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
     const int dy = dyi - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kq = lane >> 4, li = lane & 15;
-    const bool is_y = tid < NYI, is_x = !is_y && tid < NYI + NXI;
-    const int item = is_y ? tid : (is_x ? tid - NYI : 0);
-    const int oct = item % NOCT, grp = item / NOCT;          // pixel octet, 8-channel group
+    // staging items go to the highest threads: the low waves own the extra
+    // GEMM columns when the columns do not divide evenly over the waves
+    const int sit = 255 - tid;
+    const bool is_y = sit < NYI, is_x = !is_y && sit < NYI + NXI;
+    const int item = is_y ? sit : (is_x ? sit - NYI : 0);
+    const int oct = item % NOCT, grp = item / NOCT;          // pixel group, 8-channel group
     const bool want_b = a.db != nullptr && dy == 0;
     f32x4 acc[MAXC][MT];
 #pragma unroll
@@ -409,21 +415,21 @@ __global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
     const long long p_begin = (long long)chunk * a.chunk_pix;
     const long long p_end = min(p_begin + a.chunk_pix, a.npix);
     const int nst = (int)((p_end - p_begin) / P);
-    uint4 ld[10];
+    uint4 ld[Q + 2];
     auto issue = [&](int k) {
         const long long p0 = p_begin + (long long)P * min(k, nst - 1);
         const long long rowp = p0 / a.w;         // n * h + y
         const int x0 = (int)(p0 - rowp * a.w);
         if (is_y) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) ld[q] = *(const uint4*)(a.dy + (size_t)(p0 + 8 * oct + q) * CO + 8 * grp);
+            for (int q = 0; q < Q; ++q) ld[q] = *(const uint4*)(a.dy + (size_t)(p0 + Q * oct + q) * CO + 8 * grp);
         } else if (is_x) {
             const int y = (int)(rowp % a.h);
             const bool inb = y + dy >= 0 && y + dy < a.h;
             const size_t xrow = (size_t)(inb ? rowp + dy : rowp) * a.w;
 #pragma unroll
-            for (int q = 0; q < 10; ++q) {
-                int xx = x0 + 8 * oct - 1 + q;
+            for (int q = 0; q < Q + 2; ++q) {
+                int xx = x0 + Q * oct - 1 + q;
                 xx = xx < 0 ? xx + a.w : (xx >= a.w ? xx - a.w : xx);
                 const uint4 v = *(const uint4*)(a.x + (xrow + xx) * CI + 8 * grp);
                 ld[q] = inb ? v : make_uint4(0u, 0u, 0u, 0u);
@@ -436,28 +442,36 @@ __global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
         const uint32_t a = ((const uint32_t*)&lo)[c >> 1], b = ((const uint32_t*)&hi)[c >> 1];
         return __builtin_amdgcn_perm(b, a, (c & 1) ? 0x07060302u : 0x05040100u);
     };
+    // Q / 2 words of a channel row into LDS: 16-byte stores for octets, 8-byte for quartets
+    auto put = [](uint16_t* dst, const uint32_t* w) {
+        if constexpr (Q == 8) *(uint4*)dst = make_uint4(w[0], w[1], w[2], w[3]);
+        else *(uint2*)dst = make_uint2(w[0], w[1]);
+    };
     auto stage = [&]() {
         if (is_y) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                *(uint4*)&s_dy[(8 * grp + c) * LP + 8 * oct] =
-                    make_uint4(word(ld[0], ld[1], c), word(ld[2], ld[3], c), word(ld[4], ld[5], c), word(ld[6], ld[7], c));
+                uint32_t w[Q / 2];
+#pragma unroll
+                for (int k = 0; k < Q / 2; ++k) w[k] = word(ld[2 * k], ld[2 * k + 1], c);
+                put(&s_dy[(8 * grp + c) * LP + Q * oct], w);
                 if (want_b) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) bpart[c] += b2f(((const uint16_t*)&ld[q])[c]);
+                    for (int q = 0; q < Q; ++q) bpart[c] += b2f(((const uint16_t*)&ld[q])[c]);
                 }
             }
         } else if (is_x) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                // ld[q] holds pixel 8 oct - 1 + q; copy d holds pixel j + d - 1 at position j
-                const uint32_t e01 = word(ld[0], ld[1], c), e23 = word(ld[2], ld[3], c), e45 = word(ld[4], ld[5], c),
-                               e67 = word(ld[6], ld[7], c), e89 = word(ld[8], ld[9], c);
-                const uint32_t e12 = word(ld[1], ld[2], c), e34 = word(ld[3], ld[4], c), e56 = word(ld[5], ld[6], c),
-                               e78 = word(ld[7], ld[8], c);
-                *(uint4*)&s_x[(0 * CI + 8 * grp + c) * LP + 8 * oct] = make_uint4(e01, e23, e45, e67);
-                *(uint4*)&s_x[(1 * CI + 8 * grp + c) * LP + 8 * oct] = make_uint4(e12, e34, e56, e78);
-                *(uint4*)&s_x[(2 * CI + 8 * grp + c) * LP + 8 * oct] = make_uint4(e23, e45, e67, e89);
+                // ld[q] holds pixel Q oct - 1 + q; copy d holds pixel j + d - 1 at position j
+                uint32_t ev[Q / 2 + 1], od[Q / 2];   // words (2k, 2k+1) and (2k+1, 2k+2) of the Q + 2 pixels
+#pragma unroll
+                for (int k = 0; k <= Q / 2; ++k) ev[k] = word(ld[2 * k], ld[2 * k + 1], c);
+#pragma unroll
+                for (int k = 0; k < Q / 2; ++k) od[k] = word(ld[2 * k + 1], ld[2 * k + 2], c);
+                put(&s_x[(0 * CI + 8 * grp + c) * LP + Q * oct], ev);
+                put(&s_x[(1 * CI + 8 * grp + c) * LP + Q * oct], od);
+                put(&s_x[(2 * CI + 8 * grp + c) * LP + Q * oct], ev + 1);
             }
         }
     };
