@@ -352,21 +352,21 @@ __device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (ui
 // gradient, split over pixel chunks (multiples of 256 pixels).  Block
 // (chunk, dy) covers the three taps of one neighbour row as a GEMM with
 // M = output channels, N = (tap, 16-channel input group) columns, K =
-// pixels.  It walks its chunk in steps of P pixels (256, 128 or 64,
-// dividing the row width, so a step never leaves its row); per step dY and
-// the input row at x shifts -1, 0, +1 are staged in LDS transposed to
-// [channel][pixel], so that MFMA fragments (8 consecutive pixels of one
-// channel) are single 16-byte reads.  Staging is one item per thread: an
-// octet of pixels by 8 channels (16-byte loads of the octet's 8 dY pixels,
-// or of the 10 input pixels it needs at the three shifts), transposed in
-// registers and written as 16-byte LDS stores; the next step's loads are
-// issued before the current step's MFMAs.  Wave w owns the GEMM columns w,
-// w + 4, ... for every output-channel tile: per 32-pixel half step it reads
-// the dY fragments once and each input fragment once for all output tiles.
-// Partial sums go to work[chunk][co][9][ci] (and work_b[chunk][co]); a
-// second kernel adds the chunks in a fixed order.  Bias gradient (dy = 0
-// blocks): each dY thread sums its octet over the chunk's steps, and the
-// octets are added in order at the end.
+// pixels.  It walks its chunk in steps of P pixels (128 or 64, dividing the
+// row width, so a step never leaves its row); per step dY and the input row
+// at x shifts -1, 0, +1 are staged in LDS transposed to [channel][pixel], so
+// that MFMA fragments (8 consecutive pixels of one channel) are single
+// 16-byte reads.  Staging is at most one item per thread: Q pixels (4 or 8)
+// by 8 channels, 16-byte loads of the item's Q dY pixels or of the Q + 2
+// input pixels it needs at the three shifts, transposed in registers with
+// byte permutes and written as 8- or 16-byte LDS stores; the next step's
+// loads are issued before the current step's MFMAs.  Wave w owns the GEMM
+// columns w, w + 4, ... for every output-channel tile: per 32-pixel half
+// step it reads the dY fragments once and each input fragment once for all
+// output tiles.  Partial sums go to work[chunk][co][9][ci] (and
+// work_b[chunk][co]); a second kernel adds the chunks in a fixed order.
+// Bias gradient (dy = 0 blocks): each dY thread sums its item's pixels over
+// the chunk's steps, and the items are added in order at the end.
 template <int CO, int CI, int P>
 __global__ __launch_bounds__(256) void conv_wgrad2_kernel(WgradArgs a) {
     constexpr int MT = CO / 16, NJ = CI / 16, NCOL = 3 * NJ, MAXC = (NCOL + 3) / 4;
