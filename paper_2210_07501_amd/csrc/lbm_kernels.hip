@@ -249,6 +249,9 @@ __device__ __forceinline__ void block_sum(double* v, double* red /* LDS [NT/64][
 // ---------------------------------------------------------------------------
 // Fused step kernel.
 // MODE 0: step; 1: step + residual snapshot; 2: fields only (no step).
+// The float32 step kernel is held to 80 VGPRs (six waves per SIMD), which it
+// fits without spilling; left alone the compiler takes 86 (five waves), and
+// the step runs about 10% slower.  The float64 kernels would spill there.
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 0
 #endif
@@ -256,6 +259,8 @@ template <int TX, int TY, class S, class R, bool DEV, int MODE>
 __global__ __launch_bounds__(TX * TY)
 #if LBM_WAVES_PER_EU > 0
 __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+#else
+__attribute__((amdgpu_waves_per_eu((DEV && MODE == 0) ? 6 : 1)))
 #endif
 void step_kernel(StepArgs a) {
     constexpr int NT = TX * TY;
@@ -338,18 +343,18 @@ void step_kernel(StepArgs a) {
     // ---- phase 0: reference rows and temperature references ---------------
     for (int k = tid; k < LY2; k += NT) {
         const int r = I.row_off + min(max(y0 - 2 + k, -2), ny + 1) + 2;
-        s_phi0[k] = DEV ? ((const R*)a.phi0_v)[r] : R(0);
-        s_dR[k] = DEV ? ((const R*)a.phir_v)[r] : R(0);
-        s_fr[k] = DEV ? ((const R*)a.fr_v)[r] : R(0);
+        s_phi0[k] = DEV ? R(((const S*)a.phi0_v)[r]) : R(0);
+        s_dR[k] = DEV ? R(((const S*)a.phir_v)[r]) : R(0);
+        s_fr[k] = DEV ? R(((const S*)a.fr_v)[r]) : R(0);
     }
     for (int k = tid; k < LY2 + 2; k += NT) {
         const int r = I.row_off + min(max(y0 - 3 + k, -2), ny + 1) + 2;
-        s_fq[k] = DEV ? ((const R*)a.fq_v)[r] : R(0);
+        s_fq[k] = DEV ? R(((const S*)a.fq_v)[r]) : R(0);
     }
     if (DEV) {
         // per-node references: phi offsets on tile + 3, temperatures on tile + 2
         const int32_t* __restrict__ dlv = a.dl_v + I.node_off;
-        const R* __restrict__ tref = (const R*)a.tref_v + I.node_off;
+        const S* __restrict__ tref = (const S*)a.tref_v + I.node_off;
         for (int k = tid; k < LY3 * LX3; k += NT) {
             const int hy = k / LX3 - 3, hx = k % LX3 - 3;
             const int jj = y0 + hy;
@@ -361,7 +366,7 @@ void step_kernel(StepArgs a) {
             const uint32_t om = (jm >= 0 && jm < ny) ? (uint32_t)jm * (uint32_t)nx + (uint32_t)colwrap(x0 + hx) : 0u;
             s_dl[k] = (jm >= 0 && jm < ny && !dz) ? dlv[om] : 0;
             if (hy >= -2 && hy <= TY + 1 && hx >= -2 && hx <= TX + 1)
-                s_Tr[(hy + 2) * LX2 + hx + 2] = in ? tref[o] : R(0);
+                s_Tr[(hy + 2) * LX2 + hx + 2] = in ? R(tref[o]) : R(0);
         }
     }
     __syncthreads();
@@ -426,13 +431,19 @@ void step_kernel(StepArgs a) {
     const bool own_row = gj < ny;
     const bool own_ok = own_row && (x0 + tx < nx);
     R f[9], g[9], h[9];
-    R rf[9], rh[9];
-    double rg[9];   // moments of g in float64: they feed the float64 g collision
+    R rh[9];
+    double rf[9];   // moments of f and g in float64: they feed the float64 f and g collisions
+    double rg[9];
     const R Tro = DEV ? s_Tr[(ty + 2) * LX2 + tx + 2] : R(0);   // this node's T reference
     double dph_d = 0.0;   // float32 mode: phi - phi0(row), accumulated in float64
     if (own_row) {
         pull_node<S, R, 7>(src, tw, p, gi, gj, Tro, f, g, h);
-        raw_moments(f, rf);
+        {
+            double fd[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fd[q] = (double)f[q];
+            raw_moments(fd, rf);
+        }
         {
             double gd[9];
 #pragma unroll
@@ -452,12 +463,12 @@ void step_kernel(StepArgs a) {
             // references' share of it is folded into the fr table.
             int d0, dxm, dym;
             fcorr(tx, ty, gj, d0, dxm, dym);
-            rf[3] += (R)((double)dxm * DL_U);
-            rf[1] += (R)((double)dym * DL_U);
+            rf[3] += (double)dxm * DL_U;
+            rf[1] += (double)dym * DL_U;
             dph_d = (double)s_dR[ty + 2] + ((double)s_fq[ty + 2] - (double)s_fq[ty + 4]) + (double)d0 * DL_U;
 #pragma unroll
             for (int q = 0; q < 9; ++q) dph_d += (double)f[q];
-            rf[0] = (R)dph_d;
+            rf[0] = dph_d;
         }
         // LDS keeps phi relative to the node's own reference phi0(row) + dl:
         // tiny near a steady state, so the small variations of phi along the
@@ -552,10 +563,18 @@ void step_kernel(StepArgs a) {
 
     // ---- phase 2: interface normal on the tile + 1 ring ----------------------
     // n = grad phi / sqrt(|grad phi|^2 + eps^2); stored as n_x and the
-    // deviation n_y - n0_y from the reference normal, formed without
-    // cancellation: with G = G0 + g (g the deviation part),
-    //   D0 - D = (-g_y (G_y + G0_y) - G_x^2) / (D0 + D),
-    //   n_y - n0_y = (G0_y (D0 - D) + g_y D0) / (D D0).
+    // deviation n_y - n0_y from the reference normal.  With G = G0 + g (g the
+    // deviation part), D^2 = |G|^2 + eps^2 and D0^2 = G0_y^2 + eps^2:
+    //   float64:  D0 - D = (-g_y (G_y + G0_y) - G_x^2) / (D0 + D),
+    //             n_y - n0_y = (G0_y (D0 - D) + g_y D0) / (D D0);
+    //   float32:  n_y^2 - n0_y^2 = (eps^2 g_y (G_y + G0_y) - G0_y^2 G_x^2) / (D^2 D0^2),
+    //             n_y - n0_y = (n_y^2 - n0_y^2) / (n_y + n0_y).
+    // The float32 form has no cancellation at all: near a flat interface
+    // n_y - n0_y is second order in G_x, while the two terms of the float64
+    // form are first order in g_y and cancel, so in float32 their rounding
+    // (relative to g_y, not to the result) dominated the curvature of
+    // weakly driven channels.  Where n_y and n0_y differ in sign (only far
+    // from the interface, |G| ~ eps) the direct difference is used.
     for (int k = tid; k < LY1 * LX1; k += NT) {
         const int hy = k / LX1 - 1, hx = k % LX1 - 1;
         const int jj = y0 + hy;
@@ -574,10 +593,10 @@ void step_kernel(StepArgs a) {
                 dny = (G0y * dD + gy * D0) / (D * D0);
             } else {
                 const R rD = rsqrt_(D2), rD0 = rsqrt_(D02);
-                const R D = D2 * rD, D0 = D02 * rD0;
-                const R dD = (-gy * (Gy + G0y) - Gx * Gx) * rcp(D0 + D);
+                const R ny1 = Gy * rD, ny0 = G0y * rD0;
+                const R num = eps2 * gy * (Gy + G0y) - (G0y * G0y) * (Gx * Gx);
                 nxv = Gx * rD;
-                dny = (G0y * dD + gy * D0) * (rD * rD0);
+                dny = (ny1 * ny0 > R(0)) ? num * rcp((D2 * D02) * (ny1 + ny0)) : ny1 - ny0;
             }
         }
         s_nx[k] = nxv;
@@ -700,7 +719,7 @@ void step_kernel(StepArgs a) {
                     const R Tn = (Tb > R(1e-6) || Tb < R(-1e-6)) ? Tro + Tb : Tro;
                     Tb = Tb - (Tn - Tro);
                     Tr = Tn;
-                    if (own_ok) ((R*)a.tref_out)[(size_t)I.node_off + (size_t)gj * nx + gi] = Tn;
+                    if (own_ok) ((S*)a.tref_out)[(size_t)I.node_off + (size_t)gj * nx + gi] = S(Tn);
                 }
             }
             // local relaxation rates
@@ -711,16 +730,20 @@ void step_kernel(StepArgs a) {
 
             // --- ACE (Sec. 4.1): relax first central moments to M theta n ---
             // stored as f - w phi0(row of this node) - q (flux reference,
-            // float32 mode)
+            // float32 mode).  Computed in float64 in both precisions: in
+            // float32 the rounding of the collision's phi-sized terms put a
+            // steady bias into the interface flux of weakly driven channels.
             {
-                const R ph0 = s_phi0[ty + 2];
-                const R dph = phb;                                // phi - phi0(row)
+                using D = double;
+                const D uxd = ux_d, uyd = uy_d, phd = phi_d;
+                const D ux2d = uxd * uxd, uy2d = uyd * uyd, uxyd = uxd * uyd, cs2d = 1.0 / 3.0;
+                const D ph0 = (D)s_phi0[ty + 2];
+                const D dph = DEV ? dph_d : (D)phb;               // phi - phi0(row)
                 // this node's storage reference phr = phi0(row) + dl (float32
                 // mode); a check step moves it to the current phi when the node
                 // has drifted by more than 1e-6, so that near steady state the
                 // stored values stay small
-                R phr = ph0, dphr = dph;
-                double dphr_d = dph_d;
+                D phr = ph0, dphr = dph;
                 if (DEV) {
                     int32_t kdl = s_dl[(ty + 3) * LX3 + tx + 3];
                     if (MODE == 1) {
@@ -729,58 +752,61 @@ void step_kernel(StepArgs a) {
                         if (own_ok) a.dl_out[(size_t)I.node_off + (size_t)gj * nx + gi] = kdl;
                     }
                     const double dlo = (double)kdl * DL_Q;
-                    phr = (R)((double)ph0 + dlo);
-                    dphr_d = dph_d - dlo;
-                    dphr = (R)dphr_d;
+                    phr = ph0 + dlo;
+                    dphr = dph_d - dlo;
                 }
-                const R k10 = rf[3] - ux * phi;
-                const R theta = R(4) * phi * (R(1) - phi) * p.inv_W;
-                R t01;
+                const D wphi = (D)p.w_phi, Mphi = (D)p.M, iW = (D)p.inv_W;
+                const D k10 = rf[3] - uxd * phd;
+                const D theta = 4.0 * phd * (1.0 - phd) * iW;
+                D t01;
                 if (DEV) {
                     // deviation form: with k01 = kref + dk (kref the pulled
                     // references' share) and theta n = theta0 n0y + d,
                     //   t01 - A = (1 - w) dk + w M d + fr(row)
-                    const R dk01 = rf[1] - uy * phi;
-                    const R th0 = R(4) * ph0 * (R(1) - ph0) * p.inv_W;
-                    const R dth = R(4) * dph * (R(1) - phi - ph0) * p.inv_W;   // theta - theta0
-                    const R dtn = dth * nyv + th0 * s_dny[c1];                  // theta n_y - theta0 n0y
-                    t01 = dk01 + p.w_phi * (p.M * dtn - dk01) + s_fr[ty + 2];
-                    if (MODE == 1 && own_ok) flux_dev = (double)t01;
+                    const D dk01 = rf[1] - uyd * phd;
+                    const D th0 = 4.0 * ph0 * (1.0 - ph0) * iW;
+                    const D dth = 4.0 * dph * (1.0 - phd - ph0) * iW;   // theta - theta0
+                    const D dtn = dth * (D)nyv + th0 * (D)s_dny[c1];     // theta n_y - theta0 n0y
+                    t01 = dk01 + wphi * (Mphi * dtn - dk01) + (D)s_fr[ty + 2];
+                    if (MODE == 1 && own_ok) flux_dev = t01;
                 } else {
-                    const R k01 = rf[1] - uy * phi;
-                    t01 = k01 + p.w_phi * (p.M * theta * nyv - k01);
+                    const D k01 = rf[1] - uyd * phd;
+                    t01 = k01 + wphi * (Mphi * theta * (D)nyv - k01);
                 }
-                const R t10 = k10 + p.w_phi * (p.M * theta * nxv - k10);
+                const D t10 = k10 + wphi * (Mphi * theta * (D)nxv - k10);
                 // post-collision central moments minus phr * (rest central moments)
-                R c[9];
-                c[0] = dphr;                                 // 00
-                c[1] = t01 + phr * uy;                       // 01
-                c[2] = dphr * cs2 - phr * uy2;               // 02
-                c[3] = t10 + phr * ux;                       // 10
-                c[4] = -phr * uxy;                           // 11
-                c[5] = phr * ux * (cs2 + uy2);               // 12
-                c[6] = dphr * cs2 - phr * ux2;               // 20
-                c[7] = phr * uy * (cs2 + ux2);               // 21
-                c[8] = dphr * (cs2 * cs2) - phr * (cs2 * (ux2 + uy2) + ux2 * uy2);  // 22
+                D c[9];
+                c[0] = dphr;                                    // 00
+                c[1] = t01 + phr * uyd;                         // 01
+                c[2] = dphr * cs2d - phr * uy2d;                // 02
+                c[3] = t10 + phr * uxd;                         // 10
+                c[4] = -phr * uxyd;                             // 11
+                c[5] = phr * uxd * (cs2d + uy2d);               // 12
+                c[6] = dphr * cs2d - phr * ux2d;                // 20
+                c[7] = phr * uyd * (cs2d + ux2d);               // 21
+                c[8] = dphr * (cs2d * cs2d) - phr * (cs2d * (ux2d + uy2d) + ux2d * uy2d);  // 22
                 if (DEV) {
                     // minus the other central moments of q (raw: m01 = A only),
                     // the flux reference this step stores against
-                    const R A = R(2) * ((const R*)a.fqw_v)[I.row_off + gj + 2];
-                    c[2] += R(2) * A * uy;
-                    c[4] += A * ux;
-                    c[5] -= R(2) * A * uxy;
-                    c[7] -= A * ux2;
-                    c[8] += R(2) * A * ux2 * uy;
+                    const D A = 2.0 * (D)((const S*)a.fqw_v)[I.row_off + gj + 2];
+                    c[2] += 2.0 * A * uyd;
+                    c[4] += A * uxd;
+                    c[5] -= 2.0 * A * uxyd;
+                    c[7] -= A * ux2d;
+                    c[8] += 2.0 * A * ux2d * uyd;
                 }
-                central_to_raw(c, ux, uy);
-                raw_to_dist(c, f);
+                central_to_raw(c, uxd, uyd);
+                D fo[9];
+                raw_to_dist(c, fo);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) f[q] = (R)fo[q];
                 if (DEV) {
                     // the rest population takes the rounding of the other
                     // eight: the stored values sum to phi - phr in float64
                     double s8 = 0.0;
 #pragma unroll
                     for (int q = 1; q < 9; ++q) s8 += (double)f[q];
-                    f[0] = (R)(dphr_d - s8);
+                    f[0] = (R)(dphr - s8);
                 }
             }
             // --- energy (Sec. 4.3), stored as h - w Tr(this node) ---
@@ -1042,8 +1068,8 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     central_to_raw(cf, ux, uy); raw_to_dist(cf, ef);
     central_to_raw(cg, ux, uy); raw_to_dist(cg, eg);
     central_to_raw(ch, ux, uy); raw_to_dist(ch, eh);
-    const R* phi0 = (const R*)a.phi0_v + I.row_off + 2;
-    const R* fq = (const R*)a.fq_v + I.row_off + 2;
+    const S* phi0 = (const S*)a.phi0_v + I.row_off + 2;
+    const S* fq = (const S*)a.fq_v + I.row_off + 2;
     // phi-reference offset of the writer at (ii, jj): phi there minus phi0(row),
     // rounded as the step kernel stores it (float32 mode)
     auto kdl_at = [&](int ii, int jj) -> int32_t {

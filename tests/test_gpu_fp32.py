@@ -7,8 +7,8 @@ stated per quantity (relative max-norm of each distribution; u on the scale
 of the peak interface velocity):
   populations f <= 1e-6, g <= 1e-8, h <= 1e-7 after 2000 steps;
   u <= 1e-5 of the peak interface velocity after 2000 steps of the small
-  channel, at equal densities and at density ratio 2 (measured 6.2e-7 and
-  3.9e-7; the step is deterministic, so the figures reproduce exactly for a
+  channel, at equal densities and at density ratio 2 (measured 1.4e-7 and
+  2.0e-7; the step is deterministic, so the figures reproduce exactly for a
   given build);
   sum phi drifts by < 1e-8 relative over 2000 steps;
   the same population bars at the full 4096 x 2048 size after 3 steps."""
@@ -153,3 +153,4 @@ def test_density_ratio_fp32(lbm):
     du = max(np.max(np.abs(F["ux"] - R["ux"])), np.max(np.abs(F["uy"] - R["uy"])))
     print("float32 density-ratio errors", errs, "u / peak interface u", du / upk, flush=True)
     assert du <= 1e-5 * upk
+
