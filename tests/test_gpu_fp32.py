@@ -141,7 +141,7 @@ def test_density_ratio_fp32(lbm):
     """Unequal densities (rho_b = 2 below) in float32 storage, the 128 x 64
     channel heated from rest, 2000 steps: the same bars as at equal
     densities -- u within 1e-5 of the peak interface velocity (measured
-    3.9e-7; rho and u enter the g collision in float64, so 1/rho is not
+    1.7e-7; rho and u enter the g collision in float64, so 1/rho is not
     rounded into the momentum at every step) and the population bars."""
     cfg = dict(inputs.small_channel(), rho_b=2.0)
     print("case: density ratio 2, float32, small channel 2000 steps", flush=True)

@@ -112,7 +112,7 @@ def perturbed_float64_run(L, cfg, steps, eps):
 def test_end_state_sensitivity_to_the_start(lbm, kind):
     """How far two float64 runs end apart when their starts differ by one
     rounding-sized change (1e-14 on one population of one node), after the
-    step count of the float64 solve.  SRF forgets it (measured 5e-11 of the
+    step count of the float64 solve.  SRF forgets it (measured 7e-11 of the
     peak interface velocity).  NF does not: it ends 2.2e-5 of the peak away,
     and 1e-12 or 1e-10 changes give the same order (1e-5..2e-5), so the
     response is saturated rather than proportional.  At this step count the

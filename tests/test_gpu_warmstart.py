@@ -9,10 +9,10 @@ whose float32 residual levels off above the tolerance are finished in
 float64.  Checked: the network's raw errors are far below those of the
 state at rest; every channel converges from both starts and ends in the
 same steady state; it needs at least 15% fewer steps in total over the
-channels both converge on (measured here: 16%, cold / warm 1.19) and a
+channels both converge on (measured here: 18%, cold / warm 1.21) and a
 per-channel median step ratio cold / warm of at least 1.2 (measured here:
 1.30; on all 256 held-out channels:
-median 87 401 against 121 601 steps, per-channel median ratio 1.33).  The
+median 87 401 against 116 601 steps, per-channel median ratio 1.34).  The
 remaining steps are set
 by the slow viscous, thermal and interface modes, which a prediction a few
 percent off shortens only logarithmically.
