@@ -515,6 +515,9 @@ void step_kernel(StepArgs a) {
     __syncthreads();
 
     // ---- ghost rows: phi, p* mirrored, T = 2 T_w - T ------------------------
+    // (only tiles whose LDS rows reach past a wall or past the last row have
+    // any; the condition is uniform across the work-group)
+    if (y0 < 2 || y0 + TY + 2 > ny) {
     for (int k = tid; k < LY2 * LX2; k += NT) {
         const int hy = k / LX2 - 2, hx = k % LX2 - 2;
         const int jj = y0 + hy;
@@ -542,6 +545,7 @@ void step_kernel(StepArgs a) {
         }
     }
     __syncthreads();
+    }
 
     // Isotropic gradient of phi - phi0(row) at halo position (hx, hy): the
     // stencil of the LDS deviations plus that of the reference offsets,
