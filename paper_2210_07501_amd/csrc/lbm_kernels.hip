@@ -609,7 +609,8 @@ void step_kernel(StepArgs a) {
     // n = grad phi / sqrt(|grad phi|^2 + eps^2); stored as n_x and the
     // deviation n_y - n0_y from the reference normal.  With G = G0 + g (g the
     // deviation part), D^2 = |G|^2 + eps^2 and D0^2 = G0_y^2 + eps^2:
-    //   float64:  D0 - D = (-g_y (G_y + G0_y) - G_x^2) / (D0 + D),
+    //   float64 arithmetic (with a reference profile):
+    //             D0 - D = (-g_y (G_y + G0_y) - G_x^2) / (D0 + D),
     //             n_y - n0_y = (G0_y (D0 - D) + g_y D0) / (D D0);
     //   float32:  n_y^2 - n0_y^2 = (eps^2 g_y (G_y + G0_y) - G0_y^2 G_x^2) / (D^2 D0^2),
     //             n_y - n0_y = (n_y^2 - n0_y^2) / (n_y + n0_y).
@@ -630,7 +631,12 @@ void step_kernel(StepArgs a) {
             const R Gy = gy + G0y;
             const R eps2 = R(EPS_N * EPS_N);
             const R D2 = Gx * Gx + Gy * Gy + eps2, D02 = G0y * G0y + eps2;
-            if (sizeof(R) == 8) {
+            if (!DEV) {
+                // float64: no reference profile (G0 = 0, n0 = 0), n = G / D
+                const R rD = R(1) / sqrt(D2);
+                nxv = Gx * rD;
+                dny = Gy * rD;
+            } else if (sizeof(R) == 8) {
                 const R D = sqrt(D2), D0 = sqrt(D02);
                 const R dD = (-gy * (Gy + G0y) - Gx * Gx) / (D0 + D);
                 nxv = Gx / D;
