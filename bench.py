@@ -39,7 +39,7 @@ BYTES_PER_UPDATE = {0: 27 * 2 * 8, 1: 27 * 2 * 4}
 # 1.0 of the every-step kernel, the factors read off a 1 GiB device copy),
 # tile 64x8; profiles/step_kernel_4096x2048_hbm_bytes.md.  Set to None when
 # the step kernel changes until it is measured again.
-MEASURED_TRAFFIC = {0: 488.0, 1: 236.5}
+MEASURED_TRAFFIC = {0: 485.3, 1: 236.4}
 
 
 def log(*a):
