@@ -51,8 +51,10 @@ enum {
 
 typedef enum {
     LBM_FP64 = 0,        /* populations stored and collided in float64        */
-    LBM_FP32_DEV = 1     /* float32 deviations from the rest equilibrium;
-                            residual and conserved sums stay float64          */
+    LBM_FP32_DEV = 1     /* populations stored in float32 as deviations from
+                            reference equilibria; the phase-field and the
+                            hydrodynamic collisions, the residual and the
+                            conserved sums are float64                        */
 } lbm_precision;
 
 /* Parameters of one channel (lattice units; rho c_p = 1 for both fluids). */

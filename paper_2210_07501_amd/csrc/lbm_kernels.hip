@@ -17,13 +17,15 @@
 // x and y on the D2Q9 tensor lattice; they are applied in that factored form
 // and only the central moments that actually relax are formed.
 //
-// Storage: per channel, populations [3][9][ny][nx].  In float32 mode the
-// stored numbers are deviations from rest equilibria w_a X_ref with
-// X_ref = phi0(row) for f (the cold-start tanh profile), p_r for g and a
-// per-node temperature reference for h (moved to the current temperature at
-// every check); each reference is the one of the node that will pull the
-// value.  In float64 mode all references are zero and the numbers are the
-// populations.
+// Storage: per channel, populations [ny][3][9][nx] (the 27 values of a
+// lattice row are 27 consecutive runs of nx).  In float32 mode the stored
+// numbers are deviations from reference equilibria w_a X_ref: for f,
+// X_ref = phi0(row) (the cold-start tanh profile) plus a per-node offset, and
+// a flux reference on the two vertical directions; p_r for g; a per-node
+// temperature reference for h.  The per-node references move at check steps
+// when a node has drifted; each stored value is relative to its writer's
+// references, which the pulling node adds back.  In float64 mode all
+// references are zero and the numbers are the populations.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
