@@ -85,7 +85,7 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// Element index of population (d, a) at node (i, j) in a [3][9][ny][nx] block.
+// Element index of population (d, a) at node (i, j) in a channel's [ny][3][9][nx] buffer.
 __device__ __forceinline__ size_t pidx(int nx, int ny, int d, int a, int j, int i) {
     (void)ny;
     return (((size_t)j * 27 + (size_t)(d * 9 + a)) * (size_t)nx + (size_t)i);
