@@ -66,6 +66,8 @@ struct lbm_ctx {
     double* snap = nullptr;            // 4 * total_nodes
     double* partials = nullptr;        // n_tiles * 8 (capacity for the smallest tile)
     int partial_cap = 0;
+    double* chk = nullptr;             // per-block check sums, [n_inst][chk_nb][9]
+    int chk_nb = 1;
     Inst* d_inst = nullptr;
     int* d_tile_inst = nullptr;
     int tile_cap = 0;
@@ -252,6 +254,8 @@ void fin_args(lbm_ctx* c, FinArgs& f) {
     f.insts = c->d_inst;
     f.results = c->d_res;
     f.partials = c->partials;
+    f.chk = c->chk;
+    f.chk_nb = c->chk_nb;
     for (int k = 0; k < 4; ++k) f.snap[k] = c->snap + (size_t)k * c->total_nodes;
     f.step_counter = c->d_counter;
     f.tol = c->d_tol;
@@ -298,7 +302,7 @@ int enqueue_step(lbm_ctx* c, long long s) {
     if ((check || flux_switch) && c->prec == LBM_FP32_DEV) {
         FluxArgs fa;
         flux_args(c, fa);
-        hipError_t e = check ? launch_flux_next(fa, c->n_inst, c->stream)
+        hipError_t e = check ? launch_flux_next(fa, c->max_rows, c->n_inst, c->stream)
                              : launch_flux_copy(fa, c->max_rows, c->n_inst, c->stream);
         if (e != hipSuccess) return fail_hip(c, e, "flux reference launch");
     }
@@ -460,6 +464,7 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
         long long t = 0;
         for (auto& s : TILE_SHAPES) t = std::max<long long>(t, (long long)tiles_of(p, s[0], s[1], nullptr));
         max_tiles += t;
+        c->chk_nb = std::max<int>(c->chk_nb, (int)((t + CHK_TILES - 1) / CHK_TILES));
     }
     c->total_pop = pop;
     c->total_nodes = nodes;
@@ -494,13 +499,14 @@ int lbm_create(const lbm_params* params, int32_t n_inst, int32_t precision, void
     }
     c->snap = (double*)dev_alloc(c, (size_t)nodes * 4 * sizeof(double));
     c->partials = (double*)dev_alloc(c, (size_t)max_tiles * 8 * sizeof(double));
+    c->chk = (double*)dev_alloc(c, (size_t)n_inst * c->chk_nb * 9 * sizeof(double));
     c->d_inst = (Inst*)dev_alloc(c, sizeof(Inst) * n_inst);
     c->d_tile_inst = (int*)dev_alloc(c, sizeof(int) * max_tiles);
     c->d_res = (Result*)dev_alloc(c, sizeof(Result) * n_inst);
     c->d_counter = (long long*)dev_alloc(c, sizeof(long long));
     c->d_tol = (double*)dev_alloc(c, sizeof(double));
     c->d_active = (int*)dev_alloc(c, sizeof(int));
-    if (!c->popA || !c->popB || !c->phi0 || !c->phir || !c->fq || !c->fr || !c->twall || !c->snap || !c->partials || !c->d_inst || !c->d_tile_inst ||
+    if (!c->popA || !c->popB || !c->phi0 || !c->phir || !c->fq || !c->fr || !c->twall || !c->snap || !c->partials || !c->chk || !c->d_inst || !c->d_tile_inst ||
         !c->d_res || !c->d_counter || !c->d_tol || !c->d_active) {
         rc = LBM_ENOMEM;
     }

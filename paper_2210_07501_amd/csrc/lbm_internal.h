@@ -9,6 +9,8 @@ namespace lbm {
 // Residual, conserved sums and interface peak are recorded every CHECK_EVERY
 // steps (counted from initialisation).
 constexpr int CHECK_EVERY = 100;
+// Tiles per block of the check step's first pass (one tile per thread).
+constexpr int CHK_TILES = 256;
 
 // Tile shapes (nodes per workgroup, x by y) compiled for the fused step
 // kernel; the first one is the default.
@@ -82,6 +84,8 @@ struct FinArgs {
     Inst* insts;
     Result* results;
     const double* partials;
+    double* chk;                  // [instance][chk_nb][9]: per-block sums of the partials and interface peak
+    int chk_nb;                   // blocks per instance of the first check pass (capacity)
     double* snap[4];
     const long long* step_counter;
     const double* tol;
@@ -142,7 +146,7 @@ hipError_t launch_count_active(const Inst* insts, int n, int* out, hipStream_t s
 hipError_t launch_init(int prec, const InitArgs& a, int max_nodes, int n_inst, hipStream_t st);
 hipError_t launch_state(int prec, const StateArgs& a, int nodes, hipStream_t st);
 hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStream_t st);
-hipError_t launch_flux_next(const FluxArgs& a, int n_inst, hipStream_t st);
+hipError_t launch_flux_next(const FluxArgs& a, int max_rows, int n_inst, hipStream_t st);
 hipError_t launch_flux_copy(const FluxArgs& a, int max_rows, int n_inst, hipStream_t st);
 hipError_t launch_dl_flags(const Inst* insts, const int32_t* dl, int32_t* dlz, int max_chunks, int n_inst,
                            hipStream_t st);

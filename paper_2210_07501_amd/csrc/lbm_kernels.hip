@@ -965,52 +965,89 @@ void step_kernel(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-instance check: fixed-order sum of block partials, residual, interface
-// velocity peak on the phi = 1/2 level, retirement.
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
-    __shared__ double s_red[4 * 8];
-    const int inst = blockIdx.x;
-    Inst& I = a.insts[inst];
-    Result& res = a.results[inst];
-    if (!I.active) return;
-    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int t = threadIdx.x; t < I.ntiles; t += 256) {
+// Per-instance check, in two passes so that a large channel is not reduced
+// by one block.  First pass: block b of an instance sums the block partials
+// of its tiles CHK_TILES b .. CHK_TILES (b + 1) - 1 (one tile per thread,
+// fixed order) and takes the interface-velocity peak on the phi = 1/2 level
+// over its share of the columns.  The split depends only on the instance's
+// own tile count, so a channel checks the same in any batch.
+__device__ __forceinline__ double interface_u(const double* ux, const double* ph, int nx, int ny, int jstart, int i) {
+    for (int d = 0; d < ny; ++d) {
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            const int j = sgn ? jstart - d : jstart + d;
+            if ((sgn && d == 0) || j < 0 || j > ny - 2) continue;
+            const double c0 = ph[(size_t)j * nx + i] - 0.5, c1 = ph[(size_t)(j + 1) * nx + i] - 0.5;
+            if (c0 >= 0.0 && c1 < 0.0) {
+                const double t = c0 / (c0 - c1);
+                return (1.0 - t) * ux[(size_t)j * nx + i] + t * ux[(size_t)(j + 1) * nx + i];
+            }
+        }
+    }
+    return 0.0;
+}
+
+__device__ __forceinline__ double block_max(double x, double* s4 /* LDS [4] */) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] += a.partials[(size_t)(I.tile0 + t) * 8 + k];
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return fmax(fmax(s4[0], s4[1]), fmax(s4[2], s4[3]));
+}
+
+__global__ __launch_bounds__(256) void check_sums_kernel(FinArgs a) {
+    __shared__ double s_red[4 * 8];
+    __shared__ double s_pk[4];
+    const int inst = blockIdx.y, b = blockIdx.x;
+    const Inst& I = a.insts[inst];
+    if (!I.active) return;
+    const int nb = (I.ntiles + CHK_TILES - 1) / CHK_TILES;
+    if (b >= nb) return;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int t = b * CHK_TILES + (int)threadIdx.x;
+    if (t < I.ntiles) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = a.partials[(size_t)(I.tile0 + t) * 8 + k];
     }
     block_sum<256, 8>(v, s_red);
-    __syncthreads();
     // interface peak from the snapshot (ux at index 0, phi at index 3)
-    double peak = 0.0;
     const int nx = I.nx, ny = I.ny;
     const double* ux = a.snap[0] + I.node_off;
     const double* ph = a.snap[3] + I.node_off;
     int jstart = (int)I.b - 1;
     jstart = jstart < 0 ? 0 : (jstart > ny - 2 ? ny - 2 : jstart);
-    for (int i = threadIdx.x; i < nx; i += 256) {
-        double u = 0.0;
-        bool found = false;
-        for (int d = 0; d < ny && !found; ++d) {
-            for (int sgn = 0; sgn < 2 && !found; ++sgn) {
-                const int j = sgn ? jstart - d : jstart + d;
-                if ((sgn && d == 0) || j < 0 || j > ny - 2) continue;
-                const double c0 = ph[(size_t)j * nx + i] - 0.5, c1 = ph[(size_t)(j + 1) * nx + i] - 0.5;
-                if (c0 >= 0.0 && c1 < 0.0) {
-                    const double t = c0 / (c0 - c1);
-                    u = (1.0 - t) * ux[(size_t)j * nx + i] + t * ux[(size_t)(j + 1) * nx + i];
-                    found = true;
-                }
-            }
-        }
-        peak = fmax(peak, fabs(u));
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) peak = fmax(peak, __shfl_xor(peak, o, 64));
-    __shared__ double s_pk[4];
-    if ((threadIdx.x & 63) == 0) s_pk[threadIdx.x >> 6] = peak;
-    __syncthreads();
+    const int cpb = (nx + nb - 1) / nb, i0 = b * cpb, i1 = min(nx, i0 + cpb);
+    double peak = 0.0;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) peak = fmax(peak, fabs(interface_u(ux, ph, nx, ny, jstart, i)));
+    peak = block_max(peak, s_pk);
     if (threadIdx.x == 0) {
-        peak = fmax(fmax(s_pk[0], s_pk[1]), fmax(s_pk[2], s_pk[3]));
+        double* o = a.chk + ((size_t)inst * a.chk_nb + b) * 9;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = v[k];
+        o[8] = peak;
+    }
+}
+
+// Second pass, one block per instance: the first pass's block sums in a
+// fixed order, residual, sums, interface peak, retirement.
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+    __shared__ double s_red[4 * 8];
+    __shared__ double s_pk[4];
+    const int inst = blockIdx.x;
+    Inst& I = a.insts[inst];
+    Result& res = a.results[inst];
+    if (!I.active) return;
+    const int nb = (I.ntiles + CHK_TILES - 1) / CHK_TILES;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double peak = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const double* o = a.chk + ((size_t)inst * a.chk_nb + b) * 9;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] += o[k];
+        peak = fmax(peak, o[8]);
+    }
+    block_sum<256, 8>(v, s_red);
+    peak = block_max(peak, s_pk);
+    if (threadIdx.x == 0) {
         const double K = (double)CHECK_EVERY;
         double r = INFINITY;
         if (res.have_prev) {
@@ -1240,31 +1277,37 @@ __global__ __launch_bounds__(256) void tref_copy_kernel(TrefArgs a) {
 // new table (fr_next) and for the switch step that reads the old table and
 // writes against the new one (fr_sw):
 //   fr = (1 - w) (r01 + fq_read(j-1) + fq_read(j+1)) + w M theta0 n0y - 2 fq_write(j).
-// One block per channel; channels retired before this check are left alone.
+// One thread per row (grid: row blocks x channels); channels retired before
+// this check are left alone.  A thread also forms the new table of its two
+// neighbour rows (the same fixed-order sums as their own threads), so no
+// second pass is needed for the remainder tables.
 __global__ __launch_bounds__(256) void flux_next_kernel(FluxArgs a) {
-    const Inst& I = a.insts[blockIdx.x];
+    const Inst& I = a.insts[blockIdx.y];
     if (!I.active) return;
-    const int ny = I.ny;
+    const int ny = I.ny, j = blockIdx.x * 256 + (int)threadIdx.x;
+    if (j >= ny) return;
     const long long r0 = I.row_off + 2;            // row j lives at r0 + j
-    for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+    auto fq_new = [&](int jj) -> float {           // new table at row jj, 0 <= jj < ny
         double s = 0.0;
-        for (int c = 0; c < I.tiles_x; ++c) s += a.rowpart[I.rp_off + (size_t)j * I.rp_stride + c];
-        a.fq_next[r0 + j] = (float)((double)a.fq[r0 + j] + 0.5 * s / (double)I.nx);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {                        // wall images, as the set-up builds them
-        a.fq_next[r0 - 1] = -a.fq_next[r0];
-        a.fq_next[r0 + ny] = -a.fq_next[r0 + ny - 1];
+        for (int c = 0; c < I.tiles_x; ++c) s += a.rowpart[I.rp_off + (size_t)jj * I.rp_stride + c];
+        return (float)((double)a.fq[r0 + jj] + 0.5 * s / (double)I.nx);
+    };
+    const float q = fq_new(j);
+    const float qm = j > 0 ? fq_new(j - 1) : -q;          // wall images, as the set-up builds them
+    const float qp = j < ny - 1 ? fq_new(j + 1) : -q;
+    a.fq_next[r0 + j] = q;
+    if (j == 0) {
+        a.fq_next[r0 - 1] = -q;
         a.fq_next[r0 - 2] = a.fq[r0 - 2];
+    }
+    if (j == ny - 1) {
+        a.fq_next[r0 + ny] = -q;
         a.fq_next[r0 + ny + 1] = a.fq[r0 + ny + 1];
     }
-    __syncthreads();
     const double wl = 1.0 - I.w_phi;
-    for (int j = threadIdx.x; j < ny; j += blockDim.x) {
-        const double c = a.frc[r0 + j], qn = 2.0 * (double)a.fq_next[r0 + j];
-        a.fr_next[r0 + j] = (float)(c + wl * ((double)a.fq_next[r0 + j - 1] + (double)a.fq_next[r0 + j + 1]) - qn);
-        a.fr_sw[r0 + j] = (float)(c + wl * ((double)a.fq[r0 + j - 1] + (double)a.fq[r0 + j + 1]) - qn);
-    }
+    const double c = a.frc[r0 + j], qn = 2.0 * (double)q;
+    a.fr_next[r0 + j] = (float)(c + wl * ((double)qm + (double)qp) - qn);
+    a.fr_sw[r0 + j] = (float)(c + wl * ((double)a.fq[r0 + j - 1] + (double)a.fq[r0 + j + 1]) - qn);
 }
 
 // After the switch step: the new flux tables become current (channels that
@@ -1330,6 +1373,9 @@ hipError_t launch_step(int prec, const StepArgs& a, int mode, int grid, int tx, 
 }
 
 hipError_t launch_finalize(const FinArgs& a, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(check_sums_kernel, dim3(a.chk_nb, n_inst), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(n_inst), dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -1356,8 +1402,8 @@ hipError_t launch_tref_copy(const TrefArgs& a, int max_nodes, int n_inst, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_flux_next(const FluxArgs& a, int n_inst, hipStream_t st) {
-    hipLaunchKernelGGL(flux_next_kernel, dim3(n_inst), dim3(256), 0, st, a);
+hipError_t launch_flux_next(const FluxArgs& a, int max_rows, int n_inst, hipStream_t st) {
+    hipLaunchKernelGGL(flux_next_kernel, dim3((max_rows + 255) / 256, n_inst), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
