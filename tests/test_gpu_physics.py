@@ -141,7 +141,9 @@ def test_end_state_sensitivity_to_the_start(lbm, kind):
 
 @pytest.mark.xfail(strict=True, reason="NF: float64 runs whose starts differ by 1e-14 on one population end up "
                    "to 1.7e-5 of the peak interface velocity apart at this step count "
-                   "(test_end_state_sensitivity_to_the_start); float32 measured 2.5e-5")
+                   "(test_end_state_sensitivity_to_the_start; on the CPU, the oracle shows the NF start-up "
+                   "amplifying such a change 1e8-fold, test_nf_channel_amplifies_a_rounding_sized_start_change); "
+                   "float32 measured 2.5e-5")
 def test_analytic_channel_nf_float32_at_the_float32_bar(lbm):
     G32, F64, _ = float32_at_equal_steps(lbm, inputs.analytic_channel("nf"))
     peak = np.max(np.abs(an.interface_profile(F64["ux"], F64["phi"])))
