@@ -1,6 +1,7 @@
-"""Float32-deviation path (populations stored and collided in float32 as
-deviations from reference equilibria; float64 residual and sums) against the
-float64 oracle on the same seeded inputs.
+"""Float32-deviation path (populations stored in float32 as deviations from
+reference equilibria; the phase-field and hydrodynamic collisions, the
+residual and the sums in float64) against the float64 oracle on the same
+seeded inputs.
 
 Tolerances are the float32 error budget of this storage scheme, measured and
 stated per quantity (relative max-norm of each distribution; u on the scale
@@ -8,7 +9,7 @@ of the peak interface velocity):
   populations f <= 1e-6, g <= 1e-8, h <= 1e-7 after 2000 steps;
   u <= 1e-5 of the peak interface velocity after 2000 steps of the small
   channel, at equal densities and at density ratio 2 (measured 1.4e-7 and
-  2.0e-7; the step is deterministic, so the figures reproduce exactly for a
+  1.7e-7; the step is deterministic, so the figures reproduce exactly for a
   given build);
   sum phi drifts by < 1e-8 relative over 2000 steps;
   the same population bars at the full 4096 x 2048 size after 3 steps."""
